@@ -1,0 +1,165 @@
+/*
+ * kp.h -- C-ABI of the MI355X (gfx950) mu-mode product / Tucker operator library.
+ *
+ * Operations (Caliari, Cassini, Zivcovich, "A mu-mode BLAS approach for
+ * multidimensional tensor-structured problems"):
+ *   - the mu-mode product   S = T x_mu L          (Sec. 2, Definition of the
+ *     mu-mode product; S^(mu) = L T^(mu));
+ *   - the Tucker operator   S = T x_1 L_1 ... x_d L_d  (Sec. 2, Definition of
+ *     the Tucker operator);
+ *   - its gradient (not in the paper; derived from the Lemma relating the
+ *     Tucker operator to L_d (x) ... (x) L_1 and the Kronecker transpose rule,
+ *     Appendix A property 5);
+ *   - the exponential of a small matrix, the 1-D factor of the exponential of
+ *     a Kronecker sum (Sec. 3.3).
+ *
+ * Memory layout
+ *   A tensor is column-major: mode 1 is contiguous, exactly the linear order
+ *   of vec (Appendix A). Element (j_1..j_d) (0-based here) sits at offset
+ *   j_1 + m_1 (j_2 + m_2 (j_3 + ...)). A row-major array of shape
+ *   (m_1..m_d) is the same bytes as a column-major tensor of dims
+ *   (m_d..m_1); callers with row-major data reverse the dims and the factor
+ *   list (the Python binding does this).
+ *   A matrix L (rows x cols) is strided: L(i,j) at data[i*rs + j*cs]. Its
+ *   transpose is the same data with rows/cols and rs/cs swapped (the backward
+ *   pass uses that, without a copy).
+ *
+ * Ownership and synchronisation
+ *   The caller owns every buffer (device memory for tensors, factors, outputs
+ *   and workspaces). The library never allocates device memory, never frees
+ *   caller memory and never synchronises: every call only enqueues kernels on
+ *   `stream` and returns. Calls may be captured into a HIP graph.
+ *   Outputs must not overlap inputs (KP_ERR_ALIAS).
+ *
+ * Errors
+ *   Every entry point returns KP_OK (0) or a negative kp_status. Argument
+ *   errors are detected on the host before anything is enqueued; nothing is
+ *   launched then. KP_ERR_HIP reports a failed launch; kp_last_hip_error()
+ *   returns the hipError_t behind it. Faults inside kernels surface at the
+ *   caller's next synchronisation, as with any HIP call. NaN and Inf propagate
+ *   by IEEE rules; they are not checked.
+ */
+#ifndef KP_H_
+#define KP_H_
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KP_MAX_ORDER 8
+#define KP_VERSION 100 /* 1.0.0 */
+
+typedef enum {
+  KP_OK = 0,
+  KP_ERR_NULL = -1,      /* a required pointer is NULL */
+  KP_ERR_ORDER = -2,     /* d < 1 or d > KP_MAX_ORDER */
+  KP_ERR_MODE = -3,      /* mu outside 1..d */
+  KP_ERR_SHAPE = -4,     /* sizes do not match (L cols vs m_mu, output dims) */
+  KP_ERR_DTYPE = -5,     /* dtype / precision combination not supported */
+  KP_ERR_ALIAS = -6,     /* an output overlaps an input */
+  KP_ERR_WORKSPACE = -7, /* workspace missing or smaller than required */
+  KP_ERR_HIP = -8,       /* a HIP launch failed; see kp_last_hip_error() */
+  KP_ERR_VALUE = -9      /* a scalar argument is out of range */
+} kp_status;
+
+typedef enum { KP_F64 = 0, KP_F32 = 1 } kp_dtype;
+
+/* Arithmetic used by the contractions.
+ *   KP_PREC_NATIVE : FP64 MFMA for KP_F64 data, FP32 MFMA for KP_F32 data.
+ *   KP_PREC_BF16X3 : KP_F32 data only. Each operand x is split by
+ *                    round-to-nearest-even into x1 = bf16(x), x2 = bf16(x-x1);
+ *                    a*b is formed as a1 b1 + a1 b2 + a2 b1 on BF16 MFMA with
+ *                    FP32 accumulation (about 16 significant bits).
+ *   KP_PREC_BF16X6 : KP_F32 data only. Three-way split (x3 = bf16(x-x1-x2));
+ *                    adds a1 b3 + a2 b2 + a3 b1 (about FP32 accuracy).
+ * Intermediates of a chain are stored in the data type (FP32 for the BF16
+ * forms) and re-split when read. */
+typedef enum {
+  KP_PREC_NATIVE = 0,
+  KP_PREC_BF16X3 = 3,
+  KP_PREC_BF16X6 = 6
+} kp_prec;
+
+/* Order-d tensor, column-major (mode 1 contiguous), dims[0..d-1] = m_1..m_d.
+ * dims[k] >= 0; a zero size gives an empty tensor (calls then launch nothing). */
+typedef struct {
+  int32_t d;
+  int32_t dtype; /* kp_dtype */
+  int64_t dims[KP_MAX_ORDER];
+  void* data;    /* device pointer */
+} kp_tensor;
+
+/* rows x cols matrix, element (i,j) at data[i*rs + j*cs] (elements, not bytes). */
+typedef struct {
+  int64_t rows, cols;
+  int64_t rs, cs;
+  int32_t dtype; /* kp_dtype */
+  int32_t pad_;
+  void* data;    /* device pointer */
+} kp_matrix;
+
+/* ---- mu-mode product (Sec. 2, Definition of the mu-mode product) --------------
+ * S = T x_mu L: every mu-fiber of T is multiplied by L. L is n x m_mu;
+ * S has the dims of T with m_mu replaced by n. mu is 1-based. No permutation
+ * or unfolding is materialised: the kernel reads the fibers in place.
+ * If accumulate != 0, S += T x_mu L (the building block of the Kronecker-sum
+ * action, Sec. 2); otherwise S is overwritten.
+ * T, L and S must share the dtype. No workspace is needed. */
+int kp_mump(const kp_tensor* T, const kp_matrix* L, int mu, kp_tensor* S,
+            int prec, int accumulate, hipStream_t stream);
+
+/* ---- Tucker operator (Sec. 2, Definition of the Tucker operator) --------------
+ * S = T x_1 L[0] x_2 L[1] ... x_d L[d-1]. L[k] is n_k x m_k; S has dims
+ * n_1..n_d. A NULL L[k] is the identity (mode skipped, n_k = m_k).
+ * The products are applied in an order chosen to minimise flops (the
+ * operator does not depend on the order, Sec. 2); ties keep 1..d.
+ * Intermediates live in the workspace `ws` (ws_bytes >= kp_tucker_workspace).
+ * If `cache` is non-NULL it receives the forward partial products
+ * P_k = T x_1 L_1 ... x_k L_k for k = 1..d-1 in definition order, packed one
+ * after another as column-major tensors (cache_bytes >= kp_tucker_cache_size);
+ * kp_tucker_backward can reuse them. Requesting the cache forces the
+ * definition order 1..d. */
+size_t kp_tucker_workspace(const kp_tensor* T, const kp_matrix* const* L, int prec);
+size_t kp_tucker_cache_size(const kp_tensor* T, const kp_matrix* const* L);
+int kp_tucker(const kp_tensor* T, const kp_matrix* const* L, kp_tensor* S,
+              int prec, void* ws, size_t ws_bytes,
+              void* cache, size_t cache_bytes, hipStream_t stream);
+
+/* ---- gradient of the Tucker operator ------------------------------------------
+ * Given the cotangent G = dloss/dS (dims n_1..n_d):
+ *   dT    = G x_1 L_1^T ... x_d L_d^T         (dims m_1..m_d)
+ *   dL_mu = Q_mu^(mu) (P_{mu-1}^(mu))^T         (n_mu x m_mu)
+ * with P_k = T x_1 L_1 ... x_k L_k (P_0 = T) and
+ *      Q_mu = G x_d L_d^T ... x_{mu+1} L_{mu+1}^T (Q_d = G), so that Q_0 = dT.
+ * dT may be NULL, and any dL[k] may be NULL, to skip that output. The dL[k]
+ * are written with their own strides (dtype of T). `cache` is the forward
+ * cache written by kp_tucker (or NULL: the P_k are recomputed).
+ * Every L[k] must be non-NULL here. ws_bytes >= kp_tucker_backward_workspace. */
+size_t kp_tucker_backward_workspace(const kp_tensor* T, const kp_matrix* const* L,
+                                    int prec);
+int kp_tucker_backward(const kp_tensor* G, const kp_tensor* T,
+                       const kp_matrix* const* L, const void* cache,
+                       size_t cache_bytes, kp_tensor* dT, kp_matrix* const* dL,
+                       int prec, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* ---- exponential of a small matrix in FP64 (Sec. 3.3 factor build) ----------
+ * E = exp(tau * A) for the n x n column-major FP64 matrix A (device memory),
+ * n <= 256, by scaling and squaring with the degree-13 Pade approximant
+ * (Higham 2005). E is n x n column-major. ws_bytes >= kp_expm_workspace(n). */
+size_t kp_expm_workspace(int64_t n);
+int kp_expm_f64(const double* A, int64_t n, double tau, double* E, void* ws,
+                size_t ws_bytes, hipStream_t stream);
+
+/* ---- utilities ------------------------------------------------------------- */
+const char* kp_strerror(int status);
+int kp_version(void);
+int kp_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KP_H_ */
