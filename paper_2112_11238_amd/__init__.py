@@ -1,0 +1,10 @@
+"""MI355X (gfx950) mu-mode product and Tucker operator.
+
+Caliari, Cassini, Zivcovich, "A mu-mode BLAS approach for multidimensional
+tensor-structured problems": S = T x_mu L and S = T x_1 L_1 ... x_d L_d, in
+hand-written HIP kernels behind the C-ABI of include/kp.h (libkp.so), with a
+thin torch binding (ops) that only marshals arguments.
+"""
+from .ops import mump, tucker, force_tile  # noqa: F401
+
+__all__ = ["mump", "tucker", "force_tile"]

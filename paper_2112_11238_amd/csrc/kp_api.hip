@@ -1,0 +1,323 @@
+// Host runtime of the C-ABI declared in include/kp.h: argument validation,
+// mode-order planning, workspace layout and kernel launches. No allocation,
+// no synchronisation: every entry point only enqueues work on the caller's
+// stream, so calls can be captured into a HIP graph.
+#include "kp.h"
+
+#include <string.h>
+
+#include "kp_common.h"
+#include "kp_internal.h"
+
+namespace kp {
+
+thread_local int g_last_hip_error = 0;
+
+int hip_status(hipError_t e) {
+  if (e == hipSuccess) return KP_OK;
+  g_last_hip_error = static_cast<int>(e);
+  return KP_ERR_HIP;
+}
+
+size_t elem_size(int dtype) { return dtype == KP_F64 ? 8 : 4; }
+
+int64_t numel(const kp_tensor& t) {
+  int64_t s = 1;
+  for (int k = 0; k < t.d; ++k) s *= t.dims[k];
+  return s;
+}
+
+int check_tensor(const kp_tensor* t, bool need_data) {
+  if (!t) return KP_ERR_NULL;
+  if (t->d < 1 || t->d > KP_MAX_ORDER) return KP_ERR_ORDER;
+  if (t->dtype != KP_F64 && t->dtype != KP_F32) return KP_ERR_DTYPE;
+  for (int k = 0; k < t->d; ++k)
+    if (t->dims[k] < 0) return KP_ERR_SHAPE;
+  if (need_data && !t->data && numel(*t) > 0) return KP_ERR_NULL;
+  return KP_OK;
+}
+
+int check_matrix(const kp_matrix* L, int dtype) {
+  if (L->rows < 0 || L->cols < 0) return KP_ERR_SHAPE;
+  if (L->dtype != dtype) return KP_ERR_DTYPE;
+  if (!L->data && L->rows > 0 && L->cols > 0) return KP_ERR_NULL;
+  return KP_OK;
+}
+
+int check_prec(int prec, int dtype) {
+  if (prec == KP_PREC_NATIVE) return KP_OK;
+  if (prec == KP_PREC_BF16X3 || prec == KP_PREC_BF16X6)
+    return dtype == KP_F32 ? KP_OK : KP_ERR_DTYPE;
+  return KP_ERR_DTYPE;
+}
+
+int form_of(int prec, int dtype) {
+  if (prec == KP_PREC_BF16X3) return FORM_BF16X3;
+  if (prec == KP_PREC_BF16X6) return FORM_BF16X6;
+  return dtype == KP_F64 ? FORM_F64 : FORM_F32;
+}
+
+bool overlaps(const void* a, size_t abytes, const void* b, size_t bbytes) {
+  if (!a || !b || abytes == 0 || bbytes == 0) return false;
+  const char* pa = static_cast<const char*>(a);
+  const char* pb = static_cast<const char*>(b);
+  return pa < pb + bbytes && pb < pa + abytes;
+}
+
+size_t matrix_span_bytes(const kp_matrix& L) {
+  if (L.rows == 0 || L.cols == 0) return 0;
+  const int64_t last = (L.rows - 1) * L.rs + (L.cols - 1) * L.cs;
+  return static_cast<size_t>(last + 1) * elem_size(L.dtype);
+}
+
+size_t align_up(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
+
+ModeArgs mode_args(const void* X, void* Y, const int64_t* dims, int d, int mu0,
+                   const kp_matrix& L, int accumulate) {
+  ModeArgs a;
+  a.X = X;
+  a.Y = Y;
+  a.L = L.data;
+  a.Il = 1;
+  for (int k = 0; k < mu0; ++k) a.Il *= dims[k];
+  a.m = dims[mu0];
+  a.n = L.rows;
+  a.Ir = 1;
+  for (int k = mu0 + 1; k < d; ++k) a.Ir *= dims[k];
+  a.rs = L.rs;
+  a.cs = L.cs;
+  a.accumulate = accumulate;
+  return a;
+}
+
+// Minimum-flop order of the d products (dynamic programming over the set of
+// modes already applied). Applying mode mu costs 2 n_mu times the current
+// number of entries; ties keep the definition order.
+void plan_order(const int64_t* m, const int64_t* n, const bool* active, int d, int* order,
+                int* count) {
+  const int full = 1 << d;
+  double best[1 << KP_MAX_ORDER];
+  int choice[1 << KP_MAX_ORDER];
+  int target = 0;
+  for (int k = 0; k < d; ++k)
+    if (active[k]) target |= 1 << k;
+  for (int s = 0; s < full; ++s) best[s] = 1e300;
+  best[target] = 0.0;
+  // best[s] = minimal cost to finish from state s (s = applied set)
+  for (int s = full - 1; s >= 0; --s) {
+    if ((s & ~target) != 0 || s == target) continue;
+    double size = 1.0;
+    for (int k = 0; k < d; ++k) size *= static_cast<double>((s >> k) & 1 ? n[k] : m[k]);
+    for (int k = 0; k < d; ++k) {
+      if (!((target >> k) & 1) || ((s >> k) & 1)) continue;
+      const double c = 2.0 * static_cast<double>(n[k]) * size + best[s | (1 << k)];
+      if (c < best[s] * (1.0 - 1e-12)) {
+        best[s] = c;
+        choice[s] = k;
+      }
+    }
+  }
+  int s = 0, c = 0;
+  while (s != target) {
+    order[c++] = choice[s];
+    s |= 1 << choice[s];
+  }
+  *count = c;
+}
+
+struct ChainPlan {
+  int count;
+  int order[KP_MAX_ORDER];       // mode index (0-based) of each step
+  int64_t dims[KP_MAX_ORDER + 1][KP_MAX_ORDER];  // dims before step s (and after last)
+  int64_t size[KP_MAX_ORDER + 1];                // entries before step s
+};
+
+void make_chain(const kp_tensor& T, const kp_matrix* const* L, bool definition_order,
+                ChainPlan* p) {
+  const int d = T.d;
+  int64_t m[KP_MAX_ORDER], n[KP_MAX_ORDER];
+  bool active[KP_MAX_ORDER];
+  for (int k = 0; k < d; ++k) {
+    m[k] = T.dims[k];
+    active[k] = L[k] != nullptr;
+    n[k] = L[k] ? L[k]->rows : m[k];
+  }
+  if (definition_order) {
+    p->count = 0;
+    for (int k = 0; k < d; ++k)
+      if (active[k]) p->order[p->count++] = k;
+  } else {
+    plan_order(m, n, active, d, p->order, &p->count);
+  }
+  int64_t cur[KP_MAX_ORDER];
+  for (int k = 0; k < d; ++k) cur[k] = m[k];
+  for (int s = 0; s <= p->count; ++s) {
+    int64_t e = 1;
+    for (int k = 0; k < d; ++k) {
+      p->dims[s][k] = cur[k];
+      e *= cur[k];
+    }
+    p->size[s] = e;
+    if (s < p->count) cur[p->order[s]] = n[p->order[s]];
+  }
+}
+
+// Workspace for a chain: two ping-pong buffers for the intermediates
+// (steps 1..count-1), buffer (s-1)&1 for the output of step s-1.
+void chain_ws(const ChainPlan& p, size_t esize, size_t* off1, size_t* total) {
+  size_t b[2] = {0, 0};
+  for (int s = 1; s < p.count; ++s) {
+    const size_t bytes = static_cast<size_t>(p.size[s]) * esize;
+    if (bytes > b[(s - 1) & 1]) b[(s - 1) & 1] = bytes;
+  }
+  *off1 = align_up(b[0]);
+  *total = *off1 + align_up(b[1]);
+}
+
+int validate_tucker_args(const kp_tensor* T, const kp_matrix* const* L, int prec) {
+  int st = check_tensor(T, true);
+  if (st) return st;
+  if (!L) return KP_ERR_NULL;
+  for (int k = 0; k < T->d; ++k) {
+    if (!L[k]) continue;
+    st = check_matrix(L[k], T->dtype);
+    if (st) return st;
+    if (L[k]->cols != T->dims[k]) return KP_ERR_SHAPE;
+  }
+  return check_prec(prec, T->dtype);
+}
+
+size_t cache_bytes_for(const kp_tensor& T, const kp_matrix* const* L) {
+  ChainPlan p;
+  make_chain(T, L, true, &p);
+  size_t total = 0;
+  for (int s = 1; s < p.count; ++s) total += align_up(static_cast<size_t>(p.size[s]) * elem_size(T.dtype));
+  return total;
+}
+
+}  // namespace kp
+
+using namespace kp;
+
+extern "C" {
+
+int kp_version(void) { return KP_VERSION; }
+int kp_last_hip_error(void) { return g_last_hip_error; }
+
+const char* kp_strerror(int status) {
+  switch (status) {
+    case KP_OK: return "ok";
+    case KP_ERR_NULL: return "required pointer is NULL";
+    case KP_ERR_ORDER: return "tensor order outside 1..KP_MAX_ORDER";
+    case KP_ERR_MODE: return "mode outside 1..d";
+    case KP_ERR_SHAPE: return "sizes do not match";
+    case KP_ERR_DTYPE: return "unsupported dtype / precision combination";
+    case KP_ERR_ALIAS: return "output overlaps an input";
+    case KP_ERR_WORKSPACE: return "workspace missing or too small";
+    case KP_ERR_HIP: return "HIP launch failed";
+    case KP_ERR_VALUE: return "scalar argument out of range";
+    default: return "unknown status";
+  }
+}
+
+int kp_mump(const kp_tensor* T, const kp_matrix* L, int mu, kp_tensor* S, int prec,
+            int accumulate, hipStream_t stream) {
+  int st = check_tensor(T, true);
+  if (st) return st;
+  if (!L || !S) return KP_ERR_NULL;
+  if (mu < 1 || mu > T->d) return KP_ERR_MODE;
+  st = check_matrix(L, T->dtype);
+  if (st) return st;
+  st = check_tensor(S, true);
+  if (st) return st;
+  if (S->dtype != T->dtype) return KP_ERR_DTYPE;
+  st = check_prec(prec, T->dtype);
+  if (st) return st;
+  if (L->cols != T->dims[mu - 1] || S->d != T->d) return KP_ERR_SHAPE;
+  for (int k = 0; k < T->d; ++k) {
+    const int64_t want = (k == mu - 1) ? L->rows : T->dims[k];
+    if (S->dims[k] != want) return KP_ERR_SHAPE;
+  }
+  const size_t es = elem_size(T->dtype);
+  const size_t sb = static_cast<size_t>(numel(*S)) * es;
+  if (overlaps(S->data, sb, T->data, static_cast<size_t>(numel(*T)) * es) ||
+      overlaps(S->data, sb, L->data, matrix_span_bytes(*L)))
+    return KP_ERR_ALIAS;
+  if (numel(*S) == 0) return KP_OK;
+  const ModeArgs a = mode_args(T->data, S->data, T->dims, T->d, mu - 1, *L, accumulate);
+  return hip_status(launch_mode(form_of(prec, T->dtype), a, tile_override(), stream));
+}
+
+size_t kp_tucker_workspace(const kp_tensor* T, const kp_matrix* const* L, int prec) {
+  if (validate_tucker_args(T, L, prec)) return 0;
+  ChainPlan p;
+  make_chain(*T, L, false, &p);
+  size_t off1, total;
+  chain_ws(p, elem_size(T->dtype), &off1, &total);
+  // the definition-order chain (used when a cache is requested) may differ
+  ChainPlan q;
+  make_chain(*T, L, true, &q);
+  size_t off1q, totalq;
+  chain_ws(q, elem_size(T->dtype), &off1q, &totalq);
+  return total > totalq ? total : totalq;
+}
+
+size_t kp_tucker_cache_size(const kp_tensor* T, const kp_matrix* const* L) {
+  if (validate_tucker_args(T, L, KP_PREC_NATIVE)) return 0;
+  return cache_bytes_for(*T, L);
+}
+
+int kp_tucker(const kp_tensor* T, const kp_matrix* const* L, kp_tensor* S, int prec, void* ws,
+              size_t ws_bytes, void* cache, size_t cache_bytes, hipStream_t stream) {
+  int st = validate_tucker_args(T, L, prec);
+  if (st) return st;
+  if (!S) return KP_ERR_NULL;
+  st = check_tensor(S, true);
+  if (st) return st;
+  if (S->dtype != T->dtype) return KP_ERR_DTYPE;
+  if (S->d != T->d) return KP_ERR_SHAPE;
+  for (int k = 0; k < T->d; ++k)
+    if (S->dims[k] != (L[k] ? L[k]->rows : T->dims[k])) return KP_ERR_SHAPE;
+  const size_t es = elem_size(T->dtype);
+  const size_t sb = static_cast<size_t>(numel(*S)) * es;
+  if (overlaps(S->data, sb, T->data, static_cast<size_t>(numel(*T)) * es)) return KP_ERR_ALIAS;
+  for (int k = 0; k < T->d; ++k)
+    if (L[k] && overlaps(S->data, sb, L[k]->data, matrix_span_bytes(*L[k]))) return KP_ERR_ALIAS;
+
+  ChainPlan p;
+  make_chain(*T, L, cache != nullptr, &p);
+  if (cache && cache_bytes < cache_bytes_for(*T, L)) return KP_ERR_WORKSPACE;
+  size_t off1 = 0, need = 0;
+  if (!cache) {
+    chain_ws(p, es, &off1, &need);
+    if (need > 0 && (!ws || ws_bytes < need)) return KP_ERR_WORKSPACE;
+    if (need > 0 && overlaps(ws, need, S->data, sb)) return KP_ERR_ALIAS;
+  }
+  const int form = form_of(prec, T->dtype);
+  if (numel(*S) == 0) return KP_OK;
+  if (p.count == 0) {
+    // every factor is the identity: S = T
+    return hip_status(hipMemcpyAsync(S->data, T->data, sb, hipMemcpyDeviceToDevice, stream));
+  }
+  const void* src = T->data;
+  size_t cache_off = 0;
+  for (int s = 0; s < p.count; ++s) {
+    void* dst;
+    if (s == p.count - 1) {
+      dst = S->data;
+    } else if (cache) {
+      dst = static_cast<char*>(cache) + cache_off;
+      cache_off += align_up(static_cast<size_t>(p.size[s + 1]) * es);
+    } else {
+      dst = static_cast<char*>(ws) + ((s & 1) ? off1 : 0);
+    }
+    const int k = p.order[s];
+    const ModeArgs a = mode_args(src, dst, p.dims[s], T->d, k, *L[k], 0);
+    st = hip_status(launch_mode(form, a, tile_override(), stream));
+    if (st) return st;
+    src = dst;
+  }
+  return KP_OK;
+}
+
+}  // extern "C"

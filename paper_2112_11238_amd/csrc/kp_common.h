@@ -1,0 +1,45 @@
+// Internal definitions shared by the gfx950 kernels and the host runtime.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace kp {
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+
+// Arithmetic form of a contraction (values match kp_prec / kp_dtype use).
+enum Form { FORM_F64 = 0, FORM_F32 = 1, FORM_BF16X3 = 3, FORM_BF16X6 = 6 };
+
+// One mu-mode product on the three-index view of a column-major tensor:
+//   X viewed as (Il, m, Ir), Y as (Il, n, Ir),
+//   Y[a, i, b] (+)= sum_j L(i, j) X[a, j, b],   L(i, j) = L[i*rs + j*cs].
+// Il = product of the sizes before mode mu (contiguous run), Ir = product
+// of the sizes after it. Offsets: X[a + Il*(j + m*b)], Y[a + Il*(i + n*b)].
+struct ModeArgs {
+  const void* X;
+  void* Y;
+  const void* L;
+  int64_t Il, m, n, Ir;
+  int64_t rs, cs;
+  int accumulate;
+};
+
+// Tile choice for the mode kernels. nb = 16-wide blocks along n per
+// workgroup, fb = 16-wide fiber blocks per wave (4 waves per workgroup),
+// bk = k-chunk staged in LDS per step.
+struct ModeTile {
+  int nb, fb, bk;
+};
+
+// Launch one mu-mode product; returns a hipError_t.
+hipError_t launch_mode(int form, const ModeArgs& a, const ModeTile* force,
+                       hipStream_t stream);
+// Default tile for a problem (what launch_mode uses when force == nullptr).
+ModeTile default_mode_tile(int form, const ModeArgs& a);
+// Whether a tile is one of the compiled variants for this form/layout.
+bool mode_tile_supported(int form, const ModeArgs& a, const ModeTile& t);
+
+}  // namespace kp

@@ -1,0 +1,158 @@
+"""torch-facing binding of the C-ABI: argument marshalling only.
+
+Tensors use the paper's indexing: a tensor T of order d is a torch tensor of
+shape (m_1, ..., m_d) whose element T[j_1, ..., j_d] is t_{j_1...j_d}; a
+factor L_mu is a torch tensor of shape (n_mu, m_mu), any strides. Every step
+of the computation runs in libkp.so's HIP kernels; this module only builds
+descriptors, allocates outputs and workspaces through torch, and passes the
+current stream.
+
+Layout mapping. The library's tensors are column-major (mode 1 contiguous).
+A row-major (C-contiguous) torch tensor of shape (m_1..m_d) holds the same
+bytes as the column-major tensor of dims (m_d..m_1); so the binding passes
+C-contiguous tensors (making non-contiguous inputs contiguous first), with the
+dims and the factor list reversed and mode mu mapped to d+1-mu.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import KpMatrix, KpTensor, check
+
+PRECISIONS = {"native": _lib.KP_PREC_NATIVE, "bf16x3": _lib.KP_PREC_BF16X3,
+              "bf16x6": _lib.KP_PREC_BF16X6,
+              _lib.KP_PREC_NATIVE: _lib.KP_PREC_NATIVE,
+              _lib.KP_PREC_BF16X3: _lib.KP_PREC_BF16X3,
+              _lib.KP_PREC_BF16X6: _lib.KP_PREC_BF16X6}
+
+
+def lib():
+    return _lib.load()
+
+
+def _prec(prec):
+    if prec not in PRECISIONS:
+        raise ValueError(f"unknown precision {prec!r}; use 'native', 'bf16x3' or 'bf16x6'")
+    return PRECISIONS[prec]
+
+
+def _dtype_code(t):
+    if t.dtype == torch.float64:
+        return _lib.KP_F64
+    if t.dtype == torch.float32:
+        return _lib.KP_F32
+    raise TypeError(f"unsupported dtype {t.dtype}; use float64 or float32")
+
+
+def _canon(t):
+    """The tensor as a C-contiguous torch tensor (library dims = reversed shape)."""
+    if t.dim() == 0:
+        raise ValueError("a tensor of order >= 1 is required")
+    return t if t.is_contiguous() else t.contiguous()
+
+
+def _tdesc(t, rev):
+    d = t.dim()
+    if d > _lib.KP_MAX_ORDER:
+        raise ValueError(f"order {d} exceeds {_lib.KP_MAX_ORDER}")
+    desc = KpTensor()
+    desc.d = d
+    desc.dtype = _dtype_code(t)
+    dims = list(t.shape)
+    if rev:
+        dims = dims[::-1]
+    for k in range(d):
+        desc.dims[k] = dims[k]
+    desc.data = t.data_ptr() if t.numel() > 0 else None
+    return desc
+
+
+def _mdesc(L):
+    if L.dim() != 2:
+        raise ValueError("factors must be matrices")
+    desc = KpMatrix()
+    desc.rows, desc.cols = L.shape
+    desc.rs, desc.cs = L.stride()
+    desc.dtype = _dtype_code(L)
+    desc.data = L.data_ptr() if L.numel() > 0 else None
+    return desc
+
+
+def _mlist(descs):
+    arr = (ctypes.POINTER(KpMatrix) * len(descs))()
+    for k, dsc in enumerate(descs):
+        arr[k] = ctypes.pointer(dsc) if dsc is not None else None
+    return arr
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _check_device(*ts):
+    for t in ts:
+        if t is not None and not t.is_cuda:
+            raise ValueError("libkp operates on GPU tensors only (no CPU path)")
+
+
+def mump(T, L, mu, prec="native", out=None, accumulate=False):
+    """S = T x_mu L (mu is 1-based, as in the paper)."""
+    _check_device(T, L)
+    d = T.dim()
+    if not 1 <= mu <= d:
+        raise ValueError(f"mode {mu} outside 1..{d}")
+    Tc = _canon(T)
+    shape = list(T.shape)
+    shape[mu - 1] = L.shape[0]
+    if out is None:
+        if accumulate:
+            raise ValueError("accumulate needs an output tensor")
+        out = torch.empty(shape, dtype=T.dtype, device=T.device)
+    elif list(out.shape) != shape or not out.is_contiguous():
+        raise ValueError("output must be a contiguous tensor of the result's shape")
+    td, sd = _tdesc(Tc, True), _tdesc(out, True)
+    st = lib().kp_mump(ctypes.byref(td), ctypes.byref(_mdesc(L)), d + 1 - mu, ctypes.byref(sd),
+                       _prec(prec), 1 if accumulate else 0, _stream())
+    check(st, "kp_mump")
+    return out
+
+
+def _tucker_call(T, Ls, prec, want_cache):
+    _check_device(T, *Ls)
+    d = T.dim()
+    if len(Ls) != d:
+        raise ValueError(f"need {d} factors, got {len(Ls)}")
+    Tc = _canon(T)
+    shape = [T.shape[k] if Ls[k] is None else Ls[k].shape[0] for k in range(d)]
+    out = torch.empty(shape, dtype=T.dtype, device=T.device)
+    mds = [None if L is None else _mdesc(L) for L in Ls]
+    mds = mds[::-1]
+    td, sd = _tdesc(Tc, True), _tdesc(out, True)
+    arr = _mlist(mds)
+    p = _prec(prec)
+    lb = lib()
+    ws_bytes = lb.kp_tucker_workspace(ctypes.byref(td), arr, p)
+    ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=T.device)
+    cache = None
+    cache_ptr, cache_bytes = None, 0
+    if want_cache:
+        cache_bytes = lb.kp_tucker_cache_size(ctypes.byref(td), arr)
+        cache = torch.empty(max(cache_bytes, 1), dtype=torch.uint8, device=T.device)
+        cache_ptr = cache.data_ptr()
+    st = lb.kp_tucker(ctypes.byref(td), arr, ctypes.byref(sd), p, ws.data_ptr(), ws_bytes,
+                      cache_ptr, cache_bytes, _stream())
+    check(st, "kp_tucker")
+    return out, cache
+
+
+def tucker(T, Ls, prec="native"):
+    """S = T x_1 L_1 x_2 ... x_d L_d. ``Ls[k] = None`` is the identity."""
+    return _tucker_call(T, Ls, prec, False)[0]
+
+
+def force_tile(nb=0, fb=0, bk=0):
+    """Force the mode-kernel tile for later launches (nb=0 resets)."""
+    check(lib().kp_force_tile(nb, fb, bk), "kp_force_tile")

@@ -1,0 +1,175 @@
+"""GPU parity of the mu-mode product and the Tucker operator against the FP64
+oracle, element by element, through the C-ABI (libkp.so)."""
+import numpy as np
+import pytest
+import torch
+
+import kp_workloads
+import oracle
+from gpu_util import cast64, chain_bound, rel_max, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+DT = {"f64": torch.float64, "f32": torch.float32}
+FORMS = [("f64", "native"), ("f32", "native"), ("f32", "bf16x3"), ("f32", "bf16x6")]
+
+
+@pytest.fixture(scope="module")
+def kp():
+    import paper_2112_11238_amd as kp
+    return kp
+
+
+def run_mump(kp, T, L, mu, dt, prec):
+    Td, Ld = to_dev(T, DT[dt]), to_dev(L, DT[dt])
+    S = kp.mump(Td, Ld, mu, prec=prec)
+    torch.cuda.synchronize()
+    return S.double().cpu().numpy(), cast64(T, DT[dt]), cast64(L, DT[dt])
+
+
+# shapes spanning several tiles, ragged tails, size-1 modes, primes, n > 256
+MUMP_CASES = [
+    ((37,), (53,)),
+    ((50, 50), (50, 50)),
+    ((1, 7), (3, 1)),
+    ((70, 33), (65, 17)),
+    ((5, 66, 3), (17, 9, 2)),
+    ((20, 31, 17), (33, 20, 5)),
+    ((3, 1, 4, 9), (2, 5, 4, 3)),
+    ((9, 130, 7), (300, 211, 40)),
+    ((64, 16, 5), (24, 200, 129)),
+]
+
+
+@pytest.mark.parametrize("dt,prec", FORMS)
+@pytest.mark.parametrize("case", range(len(MUMP_CASES)))
+def test_mump_matches_oracle(kp, dt, prec, case):
+    m, n = MUMP_CASES[case]
+    d = len(m)
+    for mu in range(1, d + 1):
+        T, Ls = kp_workloads.random_problem(1000 + case, m, n)
+        L = Ls[mu - 1]
+        say("mump", m, n, "mu", mu, dt, prec)
+        S, T64, L64 = run_mump(kp, T, L, mu, dt, prec)
+        ref = oracle.mump(T64, L64, mu)
+        factors = [None] * d
+        factors[mu - 1] = L64
+        bound = chain_bound(T64, factors, prec, DT[dt])
+        assert S.shape == ref.shape
+        assert np.all(np.abs(S - ref) <= bound), (mu, float(np.max(np.abs(S - ref) / bound)))
+
+
+@pytest.mark.parametrize("dt,prec", FORMS)
+def test_mump_accumulate(kp, dt, prec):
+    m, n = (6, 40, 11), (6, 30, 11)
+    T, Ls = kp_workloads.random_problem(7, m, n)
+    rng = np.random.default_rng(8)
+    S0 = rng.standard_normal(n)
+    say("mump accumulate", dt, prec)
+    out = to_dev(S0, DT[dt])
+    kp.mump(to_dev(T, DT[dt]), to_dev(Ls[1], DT[dt]), 2, prec=prec, out=out, accumulate=True)
+    torch.cuda.synchronize()
+    ref = cast64(S0, DT[dt]) + oracle.mump(cast64(T, DT[dt]), cast64(Ls[1], DT[dt]), 2)
+    tol = 1e-13 if dt == "f64" else 1e-4
+    assert rel_max(out.double().cpu().numpy(), ref) < tol
+
+
+def test_mump_empty_contraction_gives_zeros(kp):
+    # m_mu = 0: every output entry is an empty sum.
+    T = np.zeros((3, 0, 4))
+    L = np.zeros((5, 0))
+    say("mump empty contraction")
+    S = kp.mump(to_dev(T, torch.float64), to_dev(L, torch.float64), 2)
+    torch.cuda.synchronize()
+    assert S.shape == (3, 5, 4)
+    assert torch.count_nonzero(S).item() == 0
+
+
+def test_mump_empty_output(kp):
+    T = np.zeros((3, 5, 0))
+    L = np.ones((4, 5))
+    say("mump empty output")
+    S = kp.mump(to_dev(T, torch.float32), to_dev(L, torch.float32), 2)
+    torch.cuda.synchronize()
+    assert S.shape == (3, 4, 0)
+
+
+def test_mump_strided_factor(kp):
+    # L given as a transposed view (column strides), as the backward uses it.
+    T, Ls = kp_workloads.random_problem(9, (12, 33, 7), (12, 21, 7))
+    Lt = to_dev(Ls[1].T.copy(), torch.float64).t()   # (21, 33) with strides (1, 21)
+    say("mump strided factor")
+    S = kp.mump(to_dev(T, torch.float64), Lt, 2)
+    torch.cuda.synchronize()
+    assert rel_max(S.cpu().numpy(), oracle.mump(T, Ls[1], 2)) < 1e-13
+
+
+# every compiled tile variant, both layouts
+TILES = {
+    "native64": [(1, 4, 16), (2, 4, 16), (2, 2, 16), (4, 2, 16), (4, 1, 16), (8, 1, 16),
+                 (8, 2, 8), (13, 1, 8), (16, 1, 8)],
+    "native32": [(1, 4, 16), (2, 4, 16), (2, 2, 16), (4, 2, 16), (4, 1, 16), (8, 1, 16),
+                 (8, 2, 16), (13, 1, 16), (16, 1, 16)],
+    "bf16": [(1, 4, 32), (2, 4, 32), (2, 2, 32), (4, 2, 32), (4, 1, 32), (8, 1, 32),
+             (8, 2, 32), (13, 1, 32), (16, 1, 32)],
+}
+
+
+@pytest.mark.parametrize("dt,prec", FORMS)
+def test_every_tile_variant(kp, dt, prec):
+    key = "bf16" if prec != "native" else ("native64" if dt == "f64" else "native32")
+    m, n = (19, 45, 13), (7, 70, 29)
+    T, Ls = kp_workloads.random_problem(11, m, n)
+    T64 = cast64(T, DT[dt])
+    try:
+        for tile in TILES[key]:
+            kp.force_tile(*tile)
+            for mu in (1, 2, 3):
+                L64 = cast64(Ls[mu - 1], DT[dt])
+                say("tile", tile, dt, prec, "mu", mu)
+                S = kp.mump(to_dev(T, DT[dt]), to_dev(Ls[mu - 1], DT[dt]), mu, prec=prec)
+                torch.cuda.synchronize()
+                ref = oracle.mump(T64, L64, mu)
+                f = [None] * 3
+                f[mu - 1] = L64
+                bound = chain_bound(T64, f, prec, DT[dt])
+                assert np.all(np.abs(S.double().cpu().numpy() - ref) <= bound), (tile, mu)
+    finally:
+        kp.force_tile(0)
+
+
+TUCKER_CASES = [
+    ((50, 50), (50, 50)),
+    ((4, 5, 6), (7, 3, 9)),
+    ((17, 1, 33, 2), (5, 4, 40, 3)),
+    ((6, 5, 4, 3, 2), (2, 3, 4, 5, 6)),
+    ((4, 4, 4, 4, 4, 4), (6, 6, 6, 6, 6, 6)),
+]
+
+
+@pytest.mark.parametrize("dt,prec", FORMS)
+@pytest.mark.parametrize("case", range(len(TUCKER_CASES)))
+def test_tucker_matches_oracle(kp, dt, prec, case):
+    m, n = TUCKER_CASES[case]
+    T, Ls = kp_workloads.random_problem(2000 + case, m, n)
+    say("tucker", m, n, dt, prec)
+    S = kp.tucker(to_dev(T, DT[dt]), [to_dev(L, DT[dt]) for L in Ls], prec=prec)
+    torch.cuda.synchronize()
+    T64 = cast64(T, DT[dt])
+    L64 = [cast64(L, DT[dt]) for L in Ls]
+    ref = oracle.tucker(T64, L64)
+    bound = chain_bound(T64, L64, prec, DT[dt])
+    got = S.double().cpu().numpy()
+    assert np.all(np.abs(got - ref) <= bound), float(np.max(np.abs(got - ref) / bound))
+
+
+def test_tucker_identity_factors(kp):
+    T, Ls = kp_workloads.random_problem(3000, (5, 6, 7), (5, 8, 7))
+    say("tucker identity factors")
+    Td = to_dev(T, torch.float64)
+    S = kp.tucker(Td, [None, to_dev(Ls[1], torch.float64), None])
+    torch.cuda.synchronize()
+    assert rel_max(S.cpu().numpy(), oracle.mump(T, Ls[1], 2)) < 1e-13
+    S2 = kp.tucker(Td, [None, None, None])
+    torch.cuda.synchronize()
+    assert torch.equal(S2, Td)
