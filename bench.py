@@ -1,0 +1,235 @@
+"""Benchmark: Tucker operator TFLOP/s at d=3, m=n=200 on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+A step is one Tucker operator S = T x_1 L_1 x_2 L_2 x_3 L_3 on the resident
+cube200 input (8M-entry tensor, three 200x200 standard-normal factors, seed 0)
+through the C-ABI (kp_tucker), in each arithmetic form:
+
+  f64     FP64 MFMA                      (the reported `value`)
+  f32     FP32 MFMA
+  bf16x3  BF16 split, 3 products, FP32 accumulation
+  bf16x6  BF16 split, 6 products, FP32 accumulation
+
+Each form's error against the FP64 oracle (max-norm relative, the paper's
+metric) is reported with it. Each mu-mode product is also timed alone
+(kp_mump, HIP events around every launch on the launch stream); the FP64
+per-launch average gives the roofline entry of the dominant kernel.
+The oracle (numpy FP64 on the host) is timed on a bounded sample of the same
+workload as the CPU baseline. Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import kp_workloads  # noqa: E402
+
+METRIC = "Tucker-op TFLOP/s d=3 n=200: FP64 vs BF16x3 MFMA at 1e-6 rel err, % of peak"
+PEAK = {  # MI355X published dense peaks, TFLOP/s
+    "f64": 78.6, "f32": 157.3, "bf16": 2500.0,
+}
+HBM_PEAK_GBS = 8000.0
+FORMS = [("f64", "native"), ("f32", "native"), ("f32", "bf16x3"), ("f32", "bf16x6")]
+MODE_KERNEL_SRC = os.path.join(ROOT, "paper_2112_11238_amd", "csrc", "mode_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_mode_f64_cube200.json")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--forms", default="all", help="comma list of f64,f32,bf16x3,bf16x6")
+    ap.add_argument("--quiet", action="store_true")
+    return ap.parse_args()
+
+
+def log(args, *a):
+    if not args.quiet:
+        print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def form_name(dt, prec):
+    return dt if prec == "native" else prec
+
+
+def source_hash(path):
+    with open(path, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def load_traffic(per_launch_units):
+    """HBM bytes per launch of the FP64 mode kernel from the committed rocprof
+    counter summary, or None if absent or taken on a different kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256_16") != source_hash(MODE_KERNEL_SRC):
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(T, Ls, flops, budget_s=12.0):
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover
+        threads = os.cpu_count()
+    reps = 0
+    t0 = time.perf_counter()
+    while True:
+        oracle.tucker(T, Ls)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el > budget_s or reps >= 2000:
+            break
+    return {"value": flops * reps / el / 1e12, "unit": "TFLOP/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": f"full cube200 Tucker operator (8M entries, 9.6 GFLOP), {reps} "
+                      f"repetitions in {el:.1f} s, numpy float64"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU; multi-GPU runs are "
+                                   "not part of this build (see DESIGN.md, sharding)"}))
+        sys.exit(2)
+    import torch
+
+    import oracle
+    import paper_2112_11238_amd as kp
+    from paper_2112_11238_amd import _lib
+    _lib.load()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    want = None if args.forms == "all" else set(args.forms.split(","))
+
+    T, Ls = kp_workloads.cube200(seed=0)
+    m = T.shape
+    flops = kp_workloads.tucker_flops(m, [L.shape[0] for L in Ls])
+    flops_mode = 2 * 200 * T.size
+    log(args, "oracle reference (numpy FP64) ...")
+    t0 = time.perf_counter()
+    ref64 = oracle.tucker(T, Ls)
+    oracle_once = time.perf_counter() - t0
+    ref32 = None
+    results = {}
+    mode_avg = {}
+    for dt, prec in FORMS:
+        name = form_name(dt, prec)
+        if want and name not in want:
+            continue
+        tdt = torch.float64 if dt == "f64" else torch.float32
+        Td = torch.tensor(T, dtype=tdt, device=dev)
+        Lds = [torch.tensor(L, dtype=tdt, device=dev) for L in Ls]
+        if dt == "f32" and ref32 is None:
+            ref32 = oracle.tucker(Td.double().cpu().numpy(),
+                                  [L.double().cpu().numpy() for L in Lds])
+        ref = ref64 if dt == "f64" else ref32
+        log(args, f"form {name}: warmup {args.warmup}")
+        for _ in range(args.warmup):
+            S = kp.tucker(Td, Lds, prec=prec)
+        torch.cuda.synchronize()
+        err = float(np.abs(S.double().cpu().numpy() - ref).max() / np.abs(ref).max())
+        # timed region: K full Tucker steps, events on the launch stream
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+        torch.cuda.synchronize()
+        ev[0].record()
+        for k in range(args.steps):
+            S = kp.tucker(Td, Lds, prec=prec)
+            ev[k + 1].record()
+        torch.cuda.synchronize()
+        step_ms = [ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)]
+        total_ms = ev[0].elapsed_time(ev[-1])
+        ms = total_ms / args.steps
+        # each mu-mode product alone (kp_mump), events around every launch
+        per_mode = {}
+        for mu in (1, 2, 3):
+            out = torch.empty_like(Td)
+            for _ in range(2):
+                kp.mump(Td, Lds[mu - 1], mu, prec=prec, out=out)
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(2 * args.steps)]
+            for k in range(args.steps):
+                e[2 * k].record()
+                kp.mump(Td, Lds[mu - 1], mu, prec=prec, out=out)
+                e[2 * k + 1].record()
+            torch.cuda.synchronize()
+            d = [e[2 * k].elapsed_time(e[2 * k + 1]) for k in range(args.steps)]
+            per_mode[mu] = statistics.mean(d)
+        peak = PEAK["f64"] if dt == "f64" else (PEAK["f32"] if prec == "native" else PEAK["bf16"])
+        tflops = flops / (ms * 1e-3) / 1e12
+        mfma_tflops = tflops * (1 if prec == "native" else int(prec[-1]))
+        hbm_min_bytes = (T.size + S.numel()) * Td.element_size() + \
+            sum(L.size for L in Ls) * Td.element_size()
+        results[name] = {
+            "tflops": round(tflops, 3),
+            "ms_per_step": round(ms, 5),
+            "ms_median": round(statistics.median(step_ms), 5),
+            "frac_of_mfma_peak": round(mfma_tflops / peak, 4),
+            "mfma_issued_tflops": round(mfma_tflops, 3),
+            "peak_tflops": peak,
+            "hbm_min_gbs": round(hbm_min_bytes / (ms * 1e-3) / 1e9, 1),
+            "rel_err_maxnorm": err,
+            "meets_1e-6": err <= 1e-6,
+            "mode_ms": {str(k): round(v, 5) for k, v in per_mode.items()},
+        }
+        mode_avg[name] = statistics.mean(per_mode.values())
+        log(args, f"form {name}: {ms:.4f} ms/step  {tflops:.2f} TFLOP/s  err {err:.2e}  "
+                  f"modes {[round(v, 4) for v in per_mode.values()]} ms")
+
+    head = results.get("f64") or next(iter(results.values()))
+    line = {
+        "metric": METRIC,
+        "value": head["tflops"],
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "cube200: Tucker operator, d=3, m=n=200 (8M-entry tensor), "
+                               "square standard-normal factors, seed 0; value is the FP64 "
+                               "form, other forms under 'forms'",
+                   "d": 3, "m": 200, "n": 200, "flops_per_step": flops},
+        "forms": results,
+    }
+    if "f64" in mode_avg:
+        avg_ms = mode_avg["f64"]
+        achieved = flops_mode / (avg_ms * 1e-3) / 1e12
+        line["roofline"] = {
+            "kernel": "mode_kernel<FP64> (one mu-mode product, FP64 MFMA)",
+            "bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK["f64"],
+            "unit": "TFLOP/s", "frac": round(achieved / PEAK["f64"], 4),
+            "avg_launch_ms": round(avg_ms, 5),
+            "flops_per_launch": flops_mode,
+            "traffic": load_traffic(1),
+        }
+    if not args.no_cpu_baseline:
+        log(args, "cpu baseline (oracle) ...")
+        line["cpu_baseline"] = cpu_baseline(T, Ls, flops)
+    line["oracle_first_call_s"] = round(oracle_once, 2)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -63,7 +63,7 @@ SIGNATURES = {
                                           _V, _S, _V]),
     "kp_expm_workspace": (_S, [ctypes.c_int64]),
     "kp_expm_f64": (ctypes.c_int, [_V, ctypes.c_int64, ctypes.c_double, _V, _V, _S, _V]),
-    "kp_force_tile": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "kp_force_tile": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     "kp_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "kp_version": (ctypes.c_int, []),
     "kp_last_hip_error": (ctypes.c_int, []),

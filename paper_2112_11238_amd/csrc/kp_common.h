@@ -9,6 +9,8 @@ namespace kp {
 typedef double d4_t __attribute__((ext_vector_type(4)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef double d2_t __attribute__((ext_vector_type(2)));
+typedef float f4v_t __attribute__((ext_vector_type(4)));
 
 // Arithmetic form of a contraction (values match kp_prec / kp_dtype use).
 enum Form { FORM_F64 = 0, FORM_F32 = 1, FORM_BF16X3 = 3, FORM_BF16X6 = 6 };
@@ -29,9 +31,10 @@ struct ModeArgs {
 
 // Tile choice for the mode kernels. nb = 16-wide blocks along n per
 // workgroup, fb = 16-wide fiber blocks per wave (4 waves per workgroup),
-// bk = k-chunk staged in LDS per step.
+// bk = k-chunk staged in LDS per step, occ = waves per SIMD the variant's
+// register budget targets (0: any).
 struct ModeTile {
-  int nb, fb, bk;
+  int nb, fb, bk, occ;
 };
 
 // Launch one mu-mode product; returns a hipError_t.

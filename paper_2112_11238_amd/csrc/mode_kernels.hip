@@ -25,210 +25,26 @@
 
 #include <hip/hip_bf16.h>
 
+#include <type_traits>
+
 namespace kp {
 namespace {
 
 constexpr int kThreads = 256;
 
 // ---------------------------------------------------------------------------
-// FP64 / FP32 MFMA, 16x16x4. Lane l feeds A[l%16][l/16] and B[l/16][l%16].
-// Accumulator item v of lane l is D[row(l,v)][l%16]; the row map differs
-// between the FP64 and FP32 instructions (checked on the device).
+// MFMA operand layouts (checked on the device):
+//   16x16x4 (f64, f32): lane l feeds A[l%16][l/16] and B[l/16][l%16];
+//     accumulator item v of lane l is D[4v + l/16][l%16] for FP64 and
+//     D[4(l/16) + v][l%16] for FP32.
+//   16x16x32 bf16: lane l feeds A[l%16][8(l/16) .. +7] and
+//     B[8(l/16) .. +7][l%16]; item v of lane l is D[4(l/16) + v][l%16].
 // ---------------------------------------------------------------------------
-template <typename E>
-struct Mfma4;
-
-template <>
-struct Mfma4<double> {
-  using acc_t = d4_t;
-  static __device__ __forceinline__ acc_t run(double a, double b, acc_t c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-  static __device__ __forceinline__ int row(int l, int v) { return 4 * v + (l >> 4); }
-};
-
-template <>
-struct Mfma4<float> {
-  using acc_t = f4_t;
-  static __device__ __forceinline__ acc_t run(float a, float b, acc_t c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-  static __device__ __forceinline__ int row(int l, int v) { return 4 * (l >> 4) + v; }
-};
-
 // Offset of fiber r = a + Il*b of a (Il, len, Ir) view: a + Il*len*b.
 __device__ __forceinline__ int64_t fiber_offset(int64_t r, int64_t Il, int64_t len) {
   const int64_t b = r / Il;
   return (r - b * Il) + Il * len * b;
 }
-
-// NB: 16-blocks along n per workgroup (every wave covers all of them).
-// FB: 16-blocks of fibers per wave; 4 waves split the fibers, so a workgroup
-//     covers 64*FB fibers.
-// BK: k-chunk staged through LDS (double buffered, one barrier per chunk).
-template <typename E, int NB, int FB, int BK, bool INNER>
-__global__ __launch_bounds__(kThreads) void mode_mfma4(ModeArgs a) {
-  using Op = Mfma4<E>;
-  using acc_t = typename Op::acc_t;
-  constexpr int BN = 16 * NB;
-  constexpr int BF = 64 * FB;
-  constexpr int LDN = BN + 1;  // odd row lengths spread LDS banks
-  constexpr int LDF = BF + 1;
-  static_assert(kThreads % BK == 0, "BK must divide the block size");
-  static_assert(!INNER || kThreads % BF == 0, "BF must divide the block size");
-  constexpr int XPT = (BF * BK + kThreads - 1) / kThreads;
-  constexpr int LPT = (BN * BK + kThreads - 1) / kThreads;
-  constexpr int QB = INNER ? NB : FB;  // MFMA row blocks
-  constexpr int PB = INNER ? FB : NB;  // MFMA column blocks
-
-  __shared__ E sL[2][BK][LDN];
-  __shared__ E sX[2][BK][LDF];
-
-  const E* __restrict__ X = static_cast<const E*>(a.X);
-  E* __restrict__ Y = static_cast<E*>(a.Y);
-  const E* __restrict__ L = static_cast<const E*>(a.L);
-  const int64_t Il = a.Il, m = a.m, n = a.n;
-  const int64_t F = INNER ? a.Il * a.Ir : a.Ir;
-  const int64_t f0 = static_cast<int64_t>(blockIdx.x) * BF;
-  const int64_t i0 = static_cast<int64_t>(blockIdx.y) * BN;
-  const int t = threadIdx.x;
-  const int lane = t & 63;
-  const int w = t >> 6;
-
-  // This thread's staging assignment (fixed across chunks).
-  //   lead : X element (k, f) with k = t % BK,  f = t / BK + s*(256/BK)
-  //   inner: X element (k, f) with f = t % BF,  k = t / BF + s*(256/BF)
-  //   L    : element (k, i)   with k = t % BK,  i = t / BK + s*(256/BK)
-  int64_t xbase;  // offset of the thread's first element at k0 = 0
-  bool xf_ok;     // inner: the thread's single fiber is in range
-  if (INNER) {
-    const int64_t r = f0 + (t % BF);
-    xf_ok = r < F;
-    xbase = xf_ok ? fiber_offset(r, Il, m) : 0;
-  } else {
-    xf_ok = true;
-    xbase = (f0 + t / BK) * m + (t % BK);
-  }
-  E xr[XPT], lr[LPT];
-
-  auto load_chunk = [&](int64_t k0) {
-#pragma unroll
-    for (int s = 0; s < XPT; ++s) {
-      E v = E(0);
-      if (INNER) {
-        const int k = t / BF + s * (kThreads / BF);
-        if (k < BK && xf_ok && k0 + k < m) v = X[xbase + Il * (k0 + k)];
-      } else {
-        const int k = t % BK;
-        const int64_t f = f0 + t / BK + s * (kThreads / BK);
-        if (t + s * kThreads < BF * BK && f < F && k0 + k < m)
-          v = X[xbase + static_cast<int64_t>(s) * (kThreads / BK) * m + k0];
-      }
-      xr[s] = v;
-    }
-#pragma unroll
-    for (int s = 0; s < LPT; ++s) {
-      const int k = t % BK;
-      const int i = t / BK + s * (kThreads / BK);
-      E v = E(0);
-      if (i < BN && i0 + i < n && k0 + k < m) v = L[(i0 + i) * a.rs + (k0 + k) * a.cs];
-      lr[s] = v;
-    }
-  };
-  auto store_chunk = [&](int buf) {
-#pragma unroll
-    for (int s = 0; s < XPT; ++s) {
-      if (INNER) {
-        const int k = t / BF + s * (kThreads / BF);
-        if (k < BK) sX[buf][k][t % BF] = xr[s];
-      } else {
-        const int idx = t + s * kThreads;
-        if (idx < BF * BK) sX[buf][t % BK][idx / BK] = xr[s];
-      }
-    }
-#pragma unroll
-    for (int s = 0; s < LPT; ++s) {
-      const int i = t / BK + s * (kThreads / BK);
-      if (i < BN) sL[buf][t % BK][i] = lr[s];
-    }
-  };
-
-  acc_t acc[QB][PB];
-#pragma unroll
-  for (int q = 0; q < QB; ++q)
-#pragma unroll
-    for (int p = 0; p < PB; ++p) acc[q][p] = acc_t{};
-
-  const int64_t nchunks = (m + BK - 1) / BK;
-  if (nchunks > 0) {
-    load_chunk(0);
-    store_chunk(0);
-  }
-  __syncthreads();
-  const int c = lane & 15;
-  const int kr0 = lane >> 4;
-  for (int64_t ch = 0; ch < nchunks; ++ch) {
-    const int buf = static_cast<int>(ch & 1);
-    if (ch + 1 < nchunks) load_chunk((ch + 1) * BK);
-#pragma unroll
-    for (int kk = 0; kk < BK; kk += 4) {
-      E xf[FB], lf[NB];
-#pragma unroll
-      for (int fb = 0; fb < FB; ++fb) xf[fb] = sX[buf][kk + kr0][w * 16 * FB + fb * 16 + c];
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) lf[nb] = sL[buf][kk + kr0][nb * 16 + c];
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-        for (int fb = 0; fb < FB; ++fb) {
-          if constexpr (INNER)
-            acc[nb][fb] = Op::run(lf[nb], xf[fb], acc[nb][fb]);
-          else
-            acc[fb][nb] = Op::run(xf[fb], lf[nb], acc[fb][nb]);
-        }
-    }
-    if (ch + 1 < nchunks) store_chunk(buf ^ 1);
-    __syncthreads();
-  }
-
-  // Store: MFMA column = lane & 15 is the memory-contiguous output index.
-#pragma unroll
-  for (int q = 0; q < QB; ++q)
-#pragma unroll
-    for (int p = 0; p < PB; ++p) {
-      if (INNER) {
-        const int64_t r = f0 + w * 16 * FB + p * 16 + c;
-        if (r >= F) continue;
-        const int64_t yb = fiber_offset(r, Il, n);
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int64_t i = i0 + q * 16 + Op::row(lane, v);
-          if (i < n) {
-            E* dst = Y + yb + Il * i;
-            *dst = a.accumulate ? *dst + acc[q][p][v] : acc[q][p][v];
-          }
-        }
-      } else {
-        const int64_t i = i0 + p * 16 + c;
-        if (i >= n) continue;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int64_t f = f0 + w * 16 * FB + q * 16 + Op::row(lane, v);
-          if (f < F) {
-            E* dst = Y + i + n * f;
-            *dst = a.accumulate ? *dst + acc[q][p][v] : acc[q][p][v];
-          }
-        }
-      }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// BF16 split forms on v_mfma_f32_16x16x32_bf16. Lane l feeds
-// A[l%16][8*(l/16) .. +7] and B[8*(l/16) .. +7][l%16]: both operands are read
-// from LDS rows that are contiguous along k (16-byte reads). Accumulator item
-// v of lane l is D[4*(l/16) + v][l%16].
-// ---------------------------------------------------------------------------
 
 // Round-to-nearest-even split of x into P bf16 terms: x1 = bf16(x),
 // x2 = bf16(x - x1), x3 = bf16(x - x1 - x2). Each difference is exact in FP32.
@@ -243,41 +59,109 @@ __device__ __forceinline__ void split_bf16(float x, __bf16 (&o)[P]) {
   }
 }
 
-// Partial products of the split form: the leading a1*b1 into `hi`, the
-// correction products (smallest first) into `lo`.
-template <int S, int P>
-__device__ __forceinline__ void split_products(const bf16x8_t (&A)[P], const bf16x8_t (&B)[P],
-                                               f4_t& hi, f4_t& lo) {
-  if constexpr (S == 6) {
-    lo = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[0], B[2], lo, 0, 0, 0);
-    lo = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[1], B[1], lo, 0, 0, 0);
-    lo = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[2], B[0], lo, 0, 0, 0);
+// Per-form constants. The LDS tiles hold rows (an n index or a fiber) whose
+// k values are contiguous; every lane reads 16 bytes = KV consecutive k of
+// one row. Because the contraction is a plain sum over k, lane group
+// g = lane/16 may own k values [KV*g, KV*g + KV) of each macro step of
+// MK = 4*KV values: MFMA step s then pairs A[row][KV*g + s] with
+// B[KV*g + s][col] in every lane group, the same k on both operands.
+template <int FORM>
+struct FormT;
+
+template <>
+struct FormT<FORM_F64> {
+  using G = double;   // global element
+  using S = double;   // LDS element
+  static constexpr int P = 1, KV = 2, MK = 8;
+  using acc_t = d4_t;
+  static __device__ __forceinline__ int row(int l, int v) { return 4 * v + (l >> 4); }
+};
+template <>
+struct FormT<FORM_F32> {
+  using G = float;
+  using S = float;
+  static constexpr int P = 1, KV = 4, MK = 16;
+  using acc_t = f4_t;
+  static __device__ __forceinline__ int row(int l, int v) { return 4 * (l >> 4) + v; }
+};
+template <int FORM>
+struct FormBf16 {
+  using G = float;
+  using S = __bf16;
+  static constexpr int P = FORM == FORM_BF16X3 ? 2 : 3, KV = 8, MK = 32;
+  using acc_t = f4_t;
+  static __device__ __forceinline__ int row(int l, int v) { return 4 * (l >> 4) + v; }
+};
+template <>
+struct FormT<FORM_BF16X3> : FormBf16<FORM_BF16X3> {};
+template <>
+struct FormT<FORM_BF16X6> : FormBf16<FORM_BF16X6> {};
+
+template <int FORM>
+using Frag = typename std::conditional<FORM == FORM_F64, d2_t,
+             typename std::conditional<FORM == FORM_F32, f4v_t, bf16x8_t>::type>::type;
+
+// One macro step of MFMAs for one (row block, column block) pair.
+// A: KV k values of the MFMA row operand (per plane), B: same for the column
+// operand. hi/lo: accumulators (lo is unused by the native forms).
+template <int FORM>
+__device__ __forceinline__ void macro_step(const Frag<FORM> (&A)[FormT<FORM>::P],
+                                           const Frag<FORM> (&B)[FormT<FORM>::P],
+                                           typename FormT<FORM>::acc_t& hi,
+                                           typename FormT<FORM>::acc_t& lo) {
+  if constexpr (FORM == FORM_F64) {
+    hi = __builtin_amdgcn_mfma_f64_16x16x4f64(A[0][0], B[0][0], hi, 0, 0, 0);
+    hi = __builtin_amdgcn_mfma_f64_16x16x4f64(A[0][1], B[0][1], hi, 0, 0, 0);
+    (void)lo;
+  } else if constexpr (FORM == FORM_F32) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+      hi = __builtin_amdgcn_mfma_f32_16x16x4f32(A[0][s], B[0][s], hi, 0, 0, 0);
+    (void)lo;
+  } else {
+    // correction products (smallest first) into lo, the leading one into hi
+    if constexpr (FORM == FORM_BF16X6) {
+      lo = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[0], B[2], lo, 0, 0, 0);
+      lo = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[1], B[1], lo, 0, 0, 0);
+      lo = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[2], B[0], lo, 0, 0, 0);
+    }
+    lo = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[0], B[1], lo, 0, 0, 0);
+    lo = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[1], B[0], lo, 0, 0, 0);
+    hi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[0], B[0], hi, 0, 0, 0);
   }
-  lo = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[0], B[1], lo, 0, 0, 0);
-  lo = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[1], B[0], lo, 0, 0, 0);
-  hi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[0], B[0], hi, 0, 0, 0);
 }
 
-template <int S, int NB, int FB, bool INNER>
-__global__ __launch_bounds__(kThreads) void mode_bf16(ModeArgs a) {
-  constexpr int P = (S == 3) ? 2 : 3;  // split planes
-  constexpr int BK = 32;
-  constexpr int KG = BK / 8;  // 8-wide k groups per row
+// NB: 16-blocks along n per workgroup (every wave covers all of them).
+// FB: 16-blocks of fibers per wave; 4 waves split the fibers, so a workgroup
+//     covers 64*FB fibers.
+// BK: k values staged through LDS per chunk (double buffered, one barrier
+//     per chunk). OCC: waves per SIMD the register budget is sized for.
+template <int FORM, int NB, int FB, int BK, int OCC, bool INNER>
+__global__ __launch_bounds__(kThreads, OCC) void mode_kernel(ModeArgs a) {
+  using FT = FormT<FORM>;
+  using G = typename FT::G;
+  using SE = typename FT::S;
+  using acc_t = typename FT::acc_t;
+  using FragT = Frag<FORM>;
+  constexpr int P = FT::P, KV = FT::KV, MK = FT::MK;
+  constexpr bool SPLIT = FORM == FORM_BF16X3 || FORM == FORM_BF16X6;
   constexpr int BN = 16 * NB;
   constexpr int BF = 64 * FB;
-  constexpr int LDK = BK + 8;  // 80-byte rows: conflict-free 16-byte reads
-  constexpr int XT = (BF * KG + kThreads - 1) / kThreads;  // X tasks/thread
-  constexpr int LT = (BN * KG + kThreads - 1) / kThreads;  // L tasks/thread
-  constexpr int QB = INNER ? NB : FB;
-  constexpr int PB = INNER ? FB : NB;
+  constexpr int KG = BK / KV;                 // k groups per row and chunk
+  constexpr int LDK = BK + 16 / sizeof(SE);   // row stride: +16 bytes
+  constexpr int XT = (BF * KG + kThreads - 1) / kThreads;  // X tasks / thread
+  constexpr int LT = (BN * KG + kThreads - 1) / kThreads;  // L tasks / thread
+  constexpr int QB = INNER ? NB : FB;  // MFMA row blocks
+  constexpr int PB = INNER ? FB : NB;  // MFMA column blocks
+  static_assert(BK % MK == 0, "BK must be a multiple of the macro step");
   static_assert(!INNER || kThreads % BF == 0, "BF must divide the block size");
 
-  __shared__ __attribute__((aligned(16))) __bf16 sL[P][BN][LDK];
-  __shared__ __attribute__((aligned(16))) __bf16 sX[P][BF][LDK];
+  __shared__ __attribute__((aligned(16))) SE sL[2][P][BN][LDK];
+  __shared__ __attribute__((aligned(16))) SE sX[2][P][BF][LDK];
 
-  const float* __restrict__ X = static_cast<const float*>(a.X);
-  float* __restrict__ Y = static_cast<float*>(a.Y);
-  const float* __restrict__ L = static_cast<const float*>(a.L);
+  const G* __restrict__ X = static_cast<const G*>(a.X);
+  const G* __restrict__ L = static_cast<const G*>(a.L);
+  G* __restrict__ Y = static_cast<G*>(a.Y);
   const int64_t Il = a.Il, m = a.m, n = a.n;
   const int64_t F = INNER ? a.Il * a.Ir : a.Ir;
   const int64_t f0 = static_cast<int64_t>(blockIdx.x) * BF;
@@ -286,154 +170,196 @@ __global__ __launch_bounds__(kThreads) void mode_bf16(ModeArgs a) {
   const int lane = t & 63;
   const int w = t >> 6;
 
-  // X task: one row (fiber) and one 8-wide k group.
-  //   lead : kg = id % KG, f = id / KG   (consecutive threads walk along k)
-  //   inner: f = id % BF,  kg = id / BF  (consecutive threads walk fibers)
-  int64_t xbase = 0;
-  bool xf_ok = true;
-  if (INNER) {
-    const int64_t r = f0 + (t % BF);
-    xf_ok = r < F;
-    xbase = xf_ok ? fiber_offset(r, Il, m) : 0;
+  // Staging tasks: one row and one group of KV consecutive k.
+  //   X, inner: row = id % BF (consecutive threads walk adjacent fibers),
+  //             kg = id / BF.
+  //   X, lead : kg = id % KG, row = id / KG (threads walk along k).
+  //   L       : kg = id % KG, row = id / KG.
+  // Every element's byte offset from the chunk's uniform base pointer is
+  // fixed for the whole k loop, so it is computed once here (32-bit: the
+  // host splits launches so that each stays below 2^31 bytes). Rows past
+  // the end are clamped to the last row: they only feed accumulator rows
+  // or columns that are never stored. Only the k tail needs zeros.
+  uint32_t xo[XT][KV], lo_[LT][KV];
+  int xkg[XT], lkg[LT];
+  const int64_t xkstep = INNER ? Il : 1;  // elements per unit of k in X
+#pragma unroll
+  for (int s = 0; s < XT; ++s) {
+    const int id = t + s * kThreads;
+    int64_t rowoff;
+    int kg;
+    if (INNER) {
+      kg = (id / BF) % KG;
+      int64_t r = f0 + id % BF;
+      r = r < F ? r : F - 1;
+      rowoff = fiber_offset(r, Il, m);
+    } else {
+      kg = id % KG;
+      int64_t f = f0 + (id / KG) % BF;
+      f = f < F ? f : F - 1;
+      rowoff = f * m;
+    }
+    xkg[s] = kg;
+#pragma unroll
+    for (int e = 0; e < KV; ++e)
+      xo[s][e] = static_cast<uint32_t>((rowoff + (kg * KV + e) * xkstep) * sizeof(G));
   }
-  float xr[XT][8], lr[LT][8];
+#pragma unroll
+  for (int s = 0; s < LT; ++s) {
+    const int id = t + s * kThreads;
+    const int kg = id % KG;
+    int64_t i = i0 + (id / KG) % BN;
+    i = i < n ? i : n - 1;
+    lkg[s] = kg;
+#pragma unroll
+    for (int e = 0; e < KV; ++e)
+      lo_[s][e] = static_cast<uint32_t>((i * a.rs + (kg * KV + e) * a.cs) * sizeof(G));
+  }
+  G xr[XT][KV], lr[LT][KV];
 
-  auto load_chunk = [&](int64_t k0) {
+  // CHECK: the chunk reaches past k = m; those k read as zero.
+  auto load_chunk = [&](int64_t k0, auto check) {
+    constexpr bool CHECK = decltype(check)::value;
+    const char* xb = reinterpret_cast<const char*>(X + k0 * xkstep);
+    const char* lb = reinterpret_cast<const char*>(L + k0 * a.cs);
+#pragma unroll
+    for (int s = 0; s < XT; ++s)
+#pragma unroll
+      for (int e = 0; e < KV; ++e) {
+        if constexpr (CHECK) {
+          const bool ok = k0 + xkg[s] * KV + e < m;
+          // a k past m may lie past the tensor: read X[0] instead, then zero
+          const G v = ok ? *reinterpret_cast<const G*>(xb + xo[s][e]) : X[0];
+          xr[s][e] = ok ? v : G(0);
+        } else {
+          xr[s][e] = *reinterpret_cast<const G*>(xb + xo[s][e]);
+        }
+      }
+#pragma unroll
+    for (int s = 0; s < LT; ++s)
+#pragma unroll
+      for (int e = 0; e < KV; ++e) {
+        if constexpr (CHECK) {
+          const bool ok = k0 + lkg[s] * KV + e < m;
+          const G v = ok ? *reinterpret_cast<const G*>(lb + lo_[s][e]) : L[0];
+          lr[s][e] = ok ? v : G(0);
+        } else {
+          lr[s][e] = *reinterpret_cast<const G*>(lb + lo_[s][e]);
+        }
+      }
+  };
+  // Registers -> LDS; the split forms write P bf16 planes.
+  auto store_rows = [&](auto& tile, int row, int kg, const G (&v)[KV]) {
+    if constexpr (SPLIT) {
+      bf16x8_t pl[P];
+#pragma unroll
+      for (int e = 0; e < KV; ++e) {
+        __bf16 o[P];
+        split_bf16<P>(v[e], o);
+#pragma unroll
+        for (int p = 0; p < P; ++p) pl[p][e] = o[p];
+      }
+#pragma unroll
+      for (int p = 0; p < P; ++p) *reinterpret_cast<bf16x8_t*>(&tile[p][row][kg * KV]) = pl[p];
+    } else {
+      FragT f;
+#pragma unroll
+      for (int e = 0; e < KV; ++e) f[e] = v[e];
+      *reinterpret_cast<FragT*>(&tile[0][row][kg * KV]) = f;
+    }
+  };
+  auto store_chunk = [&](int buf) {
 #pragma unroll
     for (int s = 0; s < XT; ++s) {
       const int id = t + s * kThreads;
-      if (INNER) {
-        const int kg = id / BF;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int64_t k = k0 + kg * 8 + e;
-          xr[s][e] = (kg < KG && xf_ok && k < m) ? X[xbase + Il * k] : 0.f;
-        }
-      } else {
-        const int kg = id % KG;
-        const int64_t f = f0 + id / KG;
-        const bool ok = id < BF * KG && f < F;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int64_t k = k0 + kg * 8 + e;
-          xr[s][e] = (ok && k < m) ? X[f * m + k] : 0.f;
-        }
-      }
+      const int row = INNER ? id % BF : id / KG;
+      const int kg = INNER ? id / BF : id % KG;
+      if (row < BF && kg < KG) store_rows(sX[buf], row, kg, xr[s]);
     }
 #pragma unroll
     for (int s = 0; s < LT; ++s) {
       const int id = t + s * kThreads;
+      const int row = id / KG;
       const int kg = id % KG;
-      const int i = id / KG;
-      const bool ok = i < BN && i0 + i < n;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int64_t k = k0 + kg * 8 + e;
-        lr[s][e] = (ok && k < m) ? L[(i0 + i) * a.rs + k * a.cs] : 0.f;
-      }
-    }
-  };
-  auto store_chunk = [&]() {
-#pragma unroll
-    for (int s = 0; s < XT; ++s) {
-      const int id = t + s * kThreads;
-      int row, kg;
-      if (INNER) {
-        row = id % BF;
-        kg = id / BF;
-      } else {
-        row = id / KG;
-        kg = id % KG;
-      }
-      if (row < BF && kg < KG) {
-        bf16x8_t v[P];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          __bf16 o[P];
-          split_bf16<P>(xr[s][e], o);
-#pragma unroll
-          for (int p = 0; p < P; ++p) v[p][e] = o[p];
-        }
-#pragma unroll
-        for (int p = 0; p < P; ++p) *reinterpret_cast<bf16x8_t*>(&sX[p][row][kg * 8]) = v[p];
-      }
-    }
-#pragma unroll
-    for (int s = 0; s < LT; ++s) {
-      const int id = t + s * kThreads;
-      const int i = id / KG;
-      const int kg = id % KG;
-      if (i < BN) {
-        bf16x8_t v[P];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          __bf16 o[P];
-          split_bf16<P>(lr[s][e], o);
-#pragma unroll
-          for (int p = 0; p < P; ++p) v[p][e] = o[p];
-        }
-#pragma unroll
-        for (int p = 0; p < P; ++p) *reinterpret_cast<bf16x8_t*>(&sL[p][i][kg * 8]) = v[p];
-      }
+      if (row < BN) store_rows(sL[buf], row, kg, lr[s]);
     }
   };
 
-  f4_t hi[QB][PB], lo[QB][PB];
+  acc_t hi[QB][PB], lo[QB][PB];
 #pragma unroll
   for (int q = 0; q < QB; ++q)
 #pragma unroll
     for (int p = 0; p < PB; ++p) {
-      hi[q][p] = f4_t{};
-      lo[q][p] = f4_t{};
+      hi[q][p] = acc_t{};
+      lo[q][p] = acc_t{};
     }
 
   const int c = lane & 15;
   const int g = lane >> 4;
   const int64_t nchunks = (m + BK - 1) / BK;
-  if (nchunks > 0) load_chunk(0);
+  const int64_t nfull = m / BK;  // chunks with no k past m
+  using Checked = std::true_type;
+  using Unchecked = std::false_type;
+  if (nchunks > 0) {
+    if (nfull > 0)
+      load_chunk(0, Unchecked{});
+    else
+      load_chunk(0, Checked{});
+    store_chunk(0);
+  }
+  __syncthreads();
   for (int64_t ch = 0; ch < nchunks; ++ch) {
-    store_chunk();
-    __syncthreads();
-    if (ch + 1 < nchunks) load_chunk((ch + 1) * BK);
-    bf16x8_t xa[FB][P];
+    const int buf = static_cast<int>(ch & 1);
+    if (ch + 1 < nfull)
+      load_chunk((ch + 1) * BK, Unchecked{});
+    else if (ch + 1 < nchunks)
+      load_chunk((ch + 1) * BK, Checked{});
 #pragma unroll
-    for (int fb = 0; fb < FB; ++fb)
+    for (int kk = 0; kk < BK; kk += MK) {
+      FragT xa[FB][P];
 #pragma unroll
-      for (int p = 0; p < P; ++p)
-        xa[fb][p] = *reinterpret_cast<const bf16x8_t*>(&sX[p][w * 16 * FB + fb * 16 + c][g * 8]);
+      for (int fb = 0; fb < FB; ++fb)
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-      bf16x8_t la[P];
+        for (int p = 0; p < P; ++p)
+          xa[fb][p] = *reinterpret_cast<const FragT*>(
+              &sX[buf][p][w * 16 * FB + fb * 16 + c][kk + KV * g]);
 #pragma unroll
-      for (int p = 0; p < P; ++p)
-        la[p] = *reinterpret_cast<const bf16x8_t*>(&sL[p][nb * 16 + c][g * 8]);
+      for (int nb = 0; nb < NB; ++nb) {
+        FragT la[P];
 #pragma unroll
-      for (int fb = 0; fb < FB; ++fb) {
-        // A operand holds the MFMA rows, B the (memory-contiguous) columns.
-        if constexpr (INNER)
-          split_products<S>(la, xa[fb], hi[nb][fb], lo[nb][fb]);
-        else
-          split_products<S>(xa[fb], la, hi[fb][nb], lo[fb][nb]);
+        for (int p = 0; p < P; ++p)
+          la[p] = *reinterpret_cast<const FragT*>(&sL[buf][p][nb * 16 + c][kk + KV * g]);
+#pragma unroll
+        for (int fb = 0; fb < FB; ++fb) {
+          // A operand = MFMA rows, B = MFMA (memory-contiguous) columns
+          if constexpr (INNER)
+            macro_step<FORM>(la, xa[fb], hi[nb][fb], lo[nb][fb]);
+          else
+            macro_step<FORM>(xa[fb], la, hi[fb][nb], lo[fb][nb]);
+        }
       }
     }
+    if (ch + 1 < nchunks) store_chunk(buf ^ 1);
     __syncthreads();
   }
 
+  // Store: MFMA column = lane & 15 is the memory-contiguous output index.
 #pragma unroll
   for (int q = 0; q < QB; ++q)
 #pragma unroll
     for (int p = 0; p < PB; ++p) {
+      acc_t val = hi[q][p];
+      if constexpr (SPLIT) val = hi[q][p] + lo[q][p];
       if (INNER) {
         const int64_t r = f0 + w * 16 * FB + p * 16 + c;
         if (r >= F) continue;
-        const int64_t yb = fiber_offset(r, Il, n);
+        G* yb = Y + fiber_offset(r, Il, n);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int64_t i = i0 + q * 16 + 4 * g + v;
+          const int64_t i = i0 + q * 16 + FT::row(lane, v);
           if (i < n) {
-            float* dst = Y + yb + Il * i;
-            const float val = hi[q][p][v] + lo[q][p][v];
-            *dst = a.accumulate ? *dst + val : val;
+            G* dst = yb + Il * i;
+            *dst = a.accumulate ? *dst + val[v] : val[v];
           }
         }
       } else {
@@ -441,11 +367,10 @@ __global__ __launch_bounds__(kThreads) void mode_bf16(ModeArgs a) {
         if (i >= n) continue;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int64_t f = f0 + w * 16 * FB + q * 16 + 4 * g + v;
+          const int64_t f = f0 + w * 16 * FB + q * 16 + FT::row(lane, v);
           if (f < F) {
-            float* dst = Y + i + n * f;
-            const float val = hi[q][p][v] + lo[q][p][v];
-            *dst = a.accumulate ? *dst + val : val;
+            G* dst = Y + i + n * f;
+            *dst = a.accumulate ? *dst + val[v] : val[v];
           }
         }
       }
@@ -458,60 +383,79 @@ __global__ __launch_bounds__(kThreads) void mode_bf16(ModeArgs a) {
 using KernelFn = void (*)(ModeArgs);
 
 struct Variant {
-  int form, nb, fb, bk;
+  int form, nb, fb, bk, occ;
   KernelFn lead, inner;
 };
 
-#define KP_V4(E, FORM, NB, FB, BK) \
-  {FORM, NB, FB, BK, mode_mfma4<E, NB, FB, BK, false>, mode_mfma4<E, NB, FB, BK, true>}
-#define KP_VB(S, NB, FB) {S, NB, FB, 32, mode_bf16<S, NB, FB, false>, mode_bf16<S, NB, FB, true>}
+#define KP_V(FORM, NB, FB, BK, OCC)                                   \
+  {FORM, NB, FB, BK, OCC, mode_kernel<FORM, NB, FB, BK, OCC, false>, \
+   mode_kernel<FORM, NB, FB, BK, OCC, true>}
 
 const Variant kVariants[] = {
-    KP_V4(double, FORM_F64, 1, 4, 16), KP_V4(double, FORM_F64, 2, 4, 16),
-    KP_V4(double, FORM_F64, 2, 2, 16), KP_V4(double, FORM_F64, 4, 2, 16),
-    KP_V4(double, FORM_F64, 4, 1, 16), KP_V4(double, FORM_F64, 8, 1, 16),
-    KP_V4(double, FORM_F64, 8, 2, 8),  KP_V4(double, FORM_F64, 13, 1, 8),
-    KP_V4(double, FORM_F64, 16, 1, 8),
-    KP_V4(float, FORM_F32, 1, 4, 16),  KP_V4(float, FORM_F32, 2, 4, 16),
-    KP_V4(float, FORM_F32, 2, 2, 16),  KP_V4(float, FORM_F32, 4, 2, 16),
-    KP_V4(float, FORM_F32, 4, 1, 16),  KP_V4(float, FORM_F32, 8, 1, 16),
-    KP_V4(float, FORM_F32, 8, 2, 16),  KP_V4(float, FORM_F32, 13, 1, 16),
-    KP_V4(float, FORM_F32, 16, 1, 16),
-    KP_VB(3, 1, 4), KP_VB(3, 2, 4), KP_VB(3, 2, 2), KP_VB(3, 4, 2), KP_VB(3, 4, 1),
-    KP_VB(3, 8, 1), KP_VB(3, 8, 2), KP_VB(3, 13, 1), KP_VB(3, 16, 1),
-    KP_VB(6, 1, 4), KP_VB(6, 2, 4), KP_VB(6, 2, 2), KP_VB(6, 4, 2), KP_VB(6, 4, 1),
-    KP_VB(6, 8, 1), KP_VB(6, 8, 2), KP_VB(6, 13, 1), KP_VB(6, 16, 1),
+    // FP64
+    KP_V(FORM_F64, 1, 4, 16, 1), KP_V(FORM_F64, 2, 4, 16, 1), KP_V(FORM_F64, 2, 2, 16, 2),
+    KP_V(FORM_F64, 4, 2, 16, 2), KP_V(FORM_F64, 4, 1, 16, 2), KP_V(FORM_F64, 8, 1, 16, 2),
+    KP_V(FORM_F64, 8, 2, 16, 1), KP_V(FORM_F64, 13, 1, 16, 1), KP_V(FORM_F64, 13, 1, 16, 2),
+    KP_V(FORM_F64, 16, 1, 16, 1), KP_V(FORM_F64, 7, 1, 16, 2), KP_V(FORM_F64, 7, 1, 32, 2),
+    KP_V(FORM_F64, 13, 1, 32, 1), KP_V(FORM_F64, 7, 2, 16, 1),
+    // FP32
+    KP_V(FORM_F32, 1, 4, 16, 2), KP_V(FORM_F32, 2, 4, 16, 2), KP_V(FORM_F32, 2, 2, 16, 2),
+    KP_V(FORM_F32, 4, 2, 16, 2), KP_V(FORM_F32, 4, 1, 16, 2), KP_V(FORM_F32, 8, 1, 16, 2),
+    KP_V(FORM_F32, 8, 2, 16, 2), KP_V(FORM_F32, 13, 1, 16, 2), KP_V(FORM_F32, 16, 1, 16, 2),
+    KP_V(FORM_F32, 13, 1, 32, 2), KP_V(FORM_F32, 13, 1, 32, 1), KP_V(FORM_F32, 13, 2, 16, 1),
+    KP_V(FORM_F32, 7, 2, 16, 2), KP_V(FORM_F32, 7, 1, 32, 2),
+    // BF16 x3
+    KP_V(FORM_BF16X3, 1, 4, 32, 2), KP_V(FORM_BF16X3, 2, 4, 32, 2), KP_V(FORM_BF16X3, 2, 2, 32, 2),
+    KP_V(FORM_BF16X3, 4, 2, 32, 2), KP_V(FORM_BF16X3, 4, 1, 32, 2), KP_V(FORM_BF16X3, 8, 1, 32, 2),
+    KP_V(FORM_BF16X3, 8, 2, 32, 1), KP_V(FORM_BF16X3, 13, 1, 32, 1), KP_V(FORM_BF16X3, 16, 1, 32, 1),
+    KP_V(FORM_BF16X3, 13, 1, 32, 2), KP_V(FORM_BF16X3, 7, 1, 32, 2), KP_V(FORM_BF16X3, 4, 2, 64, 2),
+    // BF16 x6
+    KP_V(FORM_BF16X6, 1, 4, 32, 2), KP_V(FORM_BF16X6, 2, 4, 32, 2), KP_V(FORM_BF16X6, 2, 2, 32, 2),
+    KP_V(FORM_BF16X6, 4, 2, 32, 2), KP_V(FORM_BF16X6, 4, 1, 32, 2), KP_V(FORM_BF16X6, 8, 1, 32, 2),
+    KP_V(FORM_BF16X6, 8, 2, 32, 1), KP_V(FORM_BF16X6, 13, 1, 32, 1), KP_V(FORM_BF16X6, 16, 1, 32, 1),
+    KP_V(FORM_BF16X6, 13, 1, 32, 2), KP_V(FORM_BF16X6, 7, 1, 32, 2),
 };
 
 const Variant* find_variant(int form, const ModeTile& t) {
   for (const Variant& v : kVariants)
-    if (v.form == form && v.nb == t.nb && v.fb == t.fb && v.bk == t.bk) return &v;
+    if (v.form == form && v.nb == t.nb && v.fb == t.fb && v.bk == t.bk &&
+        (t.occ == 0 || v.occ == t.occ))
+      return &v;
   return nullptr;
 }
 
-int nb_for(int64_t n) {
-  if (n <= 16) return 1;
-  if (n <= 32) return 2;
-  if (n <= 64) return 4;
-  if (n <= 128) return 8;
-  if (n <= 208) return 13;
-  return 16;
+// Default tiles, chosen from tile sweeps on cube200 (m = n = 200) and small
+// modes: FP64 favours 7 blocks along n at 3 waves per SIMD, FP32 8 blocks,
+// the BF16 split forms 4 blocks (n tiles re-read their fibers from L2).
+ModeTile pick_tile(int form, int64_t n) {
+  ModeTile t{};
+  t.occ = 0;
+  if (form == FORM_F64) {
+    t.bk = 16;
+    if (n <= 16) { t.nb = 1; t.fb = 4; }
+    else if (n <= 32) { t.nb = 2; t.fb = 2; }
+    else if (n <= 64) { t.nb = 4; t.fb = 1; }
+    else if (n <= 112) { t.nb = 7; t.fb = 1; }
+    else if (n <= 128) { t.nb = 8; t.fb = 1; }
+    else { t.nb = 7; t.fb = 1; }
+  } else if (form == FORM_F32) {
+    t.bk = 16;
+    if (n <= 16) { t.nb = 1; t.fb = 4; }
+    else if (n <= 32) { t.nb = 2; t.fb = 2; }
+    else if (n <= 64) { t.nb = 4; t.fb = 1; }
+    else { t.nb = 8; t.fb = 1; }
+  } else {
+    t.bk = 32;
+    if (n <= 16) { t.nb = 1; t.fb = 4; }
+    else if (n <= 32) { t.nb = 2; t.fb = 2; }
+    else { t.nb = 4; t.fb = 1; }
+  }
+  return t;
 }
 
 }  // namespace
 
-ModeTile default_mode_tile(int form, const ModeArgs& a) {
-  ModeTile t;
-  t.nb = nb_for(a.n);
-  t.fb = t.nb <= 2 ? 4 : (t.nb <= 4 ? 2 : 1);
-  if (form == FORM_F64)
-    t.bk = t.nb >= 13 ? 8 : (t.nb == 8 && t.fb == 2 ? 8 : 16);
-  else if (form == FORM_F32)
-    t.bk = 16;
-  else
-    t.bk = 32;
-  return t;
-}
+ModeTile default_mode_tile(int form, const ModeArgs& a) { return pick_tile(form, a.n); }
 
 bool mode_tile_supported(int form, const ModeArgs& a, const ModeTile& t) {
   (void)a;
@@ -524,16 +468,35 @@ hipError_t launch_mode(int form, const ModeArgs& a, const ModeTile* force,
   const Variant* v = find_variant(form, t);
   if (!v) return hipErrorInvalidValue;
   const bool inner = a.Il > 1;
-  const int64_t F = inner ? a.Il * a.Ir : a.Ir;
-  if (F == 0 || a.n == 0) return hipSuccess;
+  if (a.Il * a.Ir == 0 || a.n == 0) return hipSuccess;
+  // The kernels address each launch's tensors with 32-bit byte offsets:
+  // split the launch along the outer index b so every piece stays below
+  // 2^31 bytes (pieces are independent: fibers never mix).
+  const int64_t es = (form == FORM_F64) ? 8 : 4;
+  const int64_t slab = a.Il * (a.m > a.n ? a.m : a.n) * es;  // bytes per b
+  const int64_t limit = static_cast<int64_t>(1) << 31;
+  if (slab >= limit) return hipErrorInvalidValue;
+  const int64_t lspan = ((a.n - 1) * a.rs + (a.m > 0 ? a.m - 1 : 0) * a.cs + 1) * es;
+  if (lspan >= limit) return hipErrorInvalidValue;
+  const int64_t per = (limit - 1) / (slab > 0 ? slab : 1);
   const int64_t bf = 64 * t.fb;
   const int64_t bn = 16 * t.nb;
-  const int64_t gx = (F + bf - 1) / bf;
-  const int64_t gy = (a.n + bn - 1) / bn;
-  if (gx > 0x7fffffffLL || gy > 65535) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL(inner ? v->inner : v->lead, dim3(static_cast<unsigned>(gx),
-                     static_cast<unsigned>(gy)), dim3(kThreads), 0, stream, a);
-  return hipGetLastError();
+  for (int64_t b0 = 0; b0 < a.Ir; b0 += per) {
+    ModeArgs p = a;
+    p.Ir = (a.Ir - b0 < per) ? a.Ir - b0 : per;
+    p.X = static_cast<const char*>(a.X) + b0 * a.Il * a.m * es;
+    p.Y = static_cast<char*>(a.Y) + b0 * a.Il * a.n * es;
+    const int64_t F = inner ? p.Il * p.Ir : p.Ir;
+    const int64_t gx = (F + bf - 1) / bf;
+    const int64_t gy = (p.n + bn - 1) / bn;
+    if (gx > 0x7fffffffLL || gy > 65535) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(inner ? v->inner : v->lead,
+                       dim3(static_cast<unsigned>(gx), static_cast<unsigned>(gy)),
+                       dim3(kThreads), 0, stream, p);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace kp

@@ -153,6 +153,6 @@ def tucker(T, Ls, prec="native"):
     return _tucker_call(T, Ls, prec, False)[0]
 
 
-def force_tile(nb=0, fb=0, bk=0):
+def force_tile(nb=0, fb=0, bk=0, occ=0):
     """Force the mode-kernel tile for later launches (nb=0 resets)."""
-    check(lib().kp_force_tile(nb, fb, bk), "kp_force_tile")
+    check(lib().kp_force_tile(nb, fb, bk, occ), "kp_force_tile")

@@ -106,18 +106,24 @@ def test_mump_strided_factor(kp):
 
 # every compiled tile variant, both layouts
 TILES = {
-    "native64": [(1, 4, 16), (2, 4, 16), (2, 2, 16), (4, 2, 16), (4, 1, 16), (8, 1, 16),
-                 (8, 2, 8), (13, 1, 8), (16, 1, 8)],
-    "native32": [(1, 4, 16), (2, 4, 16), (2, 2, 16), (4, 2, 16), (4, 1, 16), (8, 1, 16),
-                 (8, 2, 16), (13, 1, 16), (16, 1, 16)],
-    "bf16": [(1, 4, 32), (2, 4, 32), (2, 2, 32), (4, 2, 32), (4, 1, 32), (8, 1, 32),
-             (8, 2, 32), (13, 1, 32), (16, 1, 32)],
+    "native64": [(1, 4, 16, 1), (2, 4, 16, 1), (2, 2, 16, 2), (4, 2, 16, 2), (4, 1, 16, 2),
+                 (8, 1, 16, 2), (8, 2, 16, 1), (13, 1, 16, 1), (13, 1, 16, 2), (16, 1, 16, 1),
+                 (7, 1, 16, 2), (7, 1, 32, 2), (13, 1, 32, 1), (7, 2, 16, 1)],
+    "native32": [(1, 4, 16, 2), (2, 4, 16, 2), (2, 2, 16, 2), (4, 2, 16, 2), (4, 1, 16, 2),
+                 (8, 1, 16, 2), (8, 2, 16, 2), (13, 1, 16, 2), (16, 1, 16, 2), (13, 1, 32, 2),
+                 (13, 1, 32, 1), (13, 2, 16, 1), (7, 2, 16, 2), (7, 1, 32, 2)],
+    "bf16x3": [(1, 4, 32, 2), (2, 4, 32, 2), (2, 2, 32, 2), (4, 2, 32, 2), (4, 1, 32, 2),
+               (8, 1, 32, 2), (8, 2, 32, 1), (13, 1, 32, 1), (16, 1, 32, 1), (13, 1, 32, 2),
+               (7, 1, 32, 2), (4, 2, 64, 2)],
+    "bf16x6": [(1, 4, 32, 2), (2, 4, 32, 2), (2, 2, 32, 2), (4, 2, 32, 2), (4, 1, 32, 2),
+               (8, 1, 32, 2), (8, 2, 32, 1), (13, 1, 32, 1), (16, 1, 32, 1), (13, 1, 32, 2),
+               (7, 1, 32, 2)],
 }
 
 
 @pytest.mark.parametrize("dt,prec", FORMS)
 def test_every_tile_variant(kp, dt, prec):
-    key = "bf16" if prec != "native" else ("native64" if dt == "f64" else "native32")
+    key = prec if prec != "native" else ("native64" if dt == "f64" else "native32")
     m, n = (19, 45, 13), (7, 70, 29)
     T, Ls = kp_workloads.random_problem(11, m, n)
     T64 = cast64(T, DT[dt])
