@@ -5,6 +5,8 @@ tensor-structured problems": S = T x_mu L and S = T x_1 L_1 ... x_d L_d, in
 hand-written HIP kernels behind the C-ABI of include/kp.h (libkp.so), with a
 thin torch binding (ops) that only marshals arguments.
 """
-from .ops import mump, tucker, force_tile  # noqa: F401
+from .ops import (mump, tucker, tucker_with_cache, tucker_backward,  # noqa: F401
+                  tucker_autograd, TuckerFunction, force_tile)
 
-__all__ = ["mump", "tucker", "force_tile"]
+__all__ = ["mump", "tucker", "tucker_with_cache", "tucker_backward", "tucker_autograd",
+           "TuckerFunction", "force_tile"]

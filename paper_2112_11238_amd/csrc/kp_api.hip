@@ -195,6 +195,49 @@ size_t cache_bytes_for(const kp_tensor& T, const kp_matrix* const* L) {
   return total;
 }
 
+// Layout of the backward workspace: [P recompute region][Q ping][Q pong][gram partials]
+struct BackwardLayout {
+  size_t p_off, p_bytes;
+  size_t q_off[2], q_bytes[2];
+  size_t g_off, g_bytes;
+  size_t total;
+};
+
+void backward_layout(const kp_tensor& T, const kp_matrix* const* L, bool need_p,
+                     BackwardLayout* b) {
+  const int d = T.d;
+  const size_t es = elem_size(T.dtype);
+  int64_t m[KP_MAX_ORDER], n[KP_MAX_ORDER];
+  for (int k = 0; k < d; ++k) {
+    m[k] = T.dims[k];
+    n[k] = L[k]->rows;
+  }
+  b->p_bytes = need_p ? cache_bytes_for(T, L) : 0;
+  // Q_mu (mu = d-1 .. 1) has dims n_1..n_mu, m_{mu+1}..m_d; Q_mu goes to
+  // buffer (d - 1 - mu) & 1.
+  b->q_bytes[0] = b->q_bytes[1] = 0;
+  for (int mu = d - 1; mu >= 1; --mu) {
+    int64_t e = 1;
+    for (int k = 0; k < d; ++k) e *= (k < mu) ? n[k] : m[k];
+    const size_t bytes = static_cast<size_t>(e) * es;
+    size_t& slot = b->q_bytes[(d - 1 - mu) & 1];
+    if (bytes > slot) slot = bytes;
+  }
+  b->g_bytes = 0;
+  for (int mu = 1; mu <= d; ++mu) {
+    int64_t Il = 1, Ir = 1;
+    for (int k = 0; k < mu - 1; ++k) Il *= n[k];
+    for (int k = mu; k < d; ++k) Ir *= m[k];
+    const size_t g = gram_workspace(Il, n[mu - 1], m[mu - 1], Ir, es);
+    if (g > b->g_bytes) b->g_bytes = g;
+  }
+  b->p_off = 0;
+  b->q_off[0] = align_up(b->p_bytes);
+  b->q_off[1] = b->q_off[0] + align_up(b->q_bytes[0]);
+  b->g_off = b->q_off[1] + align_up(b->q_bytes[1]);
+  b->total = b->g_off + align_up(b->g_bytes);
+}
+
 }  // namespace kp
 
 using namespace kp;
@@ -316,6 +359,140 @@ int kp_tucker(const kp_tensor* T, const kp_matrix* const* L, kp_tensor* S, int p
     st = hip_status(launch_mode(form, a, tile_override(), stream));
     if (st) return st;
     src = dst;
+  }
+  return KP_OK;
+}
+
+size_t kp_tucker_backward_workspace(const kp_tensor* T, const kp_matrix* const* L, int prec) {
+  if (validate_tucker_args(T, L, prec)) return 0;
+  for (int k = 0; k < T->d; ++k)
+    if (!L[k]) return 0;
+  BackwardLayout b;
+  backward_layout(*T, L, true, &b);
+  return b.total;
+}
+
+int kp_tucker_backward(const kp_tensor* G, const kp_tensor* T, const kp_matrix* const* L,
+                       const void* cache, size_t cache_bytes, kp_tensor* dT,
+                       kp_matrix* const* dL, int prec, void* ws, size_t ws_bytes,
+                       hipStream_t stream) {
+  int st = validate_tucker_args(T, L, prec);
+  if (st) return st;
+  const int d = T->d;
+  for (int k = 0; k < d; ++k)
+    if (!L[k]) return KP_ERR_NULL;
+  st = check_tensor(G, true);
+  if (st) return st;
+  if (G->dtype != T->dtype) return KP_ERR_DTYPE;
+  if (G->d != d) return KP_ERR_SHAPE;
+  for (int k = 0; k < d; ++k)
+    if (G->dims[k] != L[k]->rows) return KP_ERR_SHAPE;
+  const size_t es = elem_size(T->dtype);
+  if (dT) {
+    st = check_tensor(dT, true);
+    if (st) return st;
+    if (dT->dtype != T->dtype) return KP_ERR_DTYPE;
+    if (dT->d != d) return KP_ERR_SHAPE;
+    for (int k = 0; k < d; ++k)
+      if (dT->dims[k] != T->dims[k]) return KP_ERR_SHAPE;
+  }
+  bool want_dl = false;
+  if (dL) {
+    for (int k = 0; k < d; ++k) {
+      if (!dL[k]) continue;
+      want_dl = true;
+      st = check_matrix(dL[k], T->dtype);
+      if (st) return st;
+      if (dL[k]->rows != L[k]->rows || dL[k]->cols != L[k]->cols) return KP_ERR_SHAPE;
+    }
+  }
+  const size_t need_cache = cache_bytes_for(*T, L);
+  const bool have_cache = cache != nullptr;
+  if (have_cache && cache_bytes < need_cache) return KP_ERR_WORKSPACE;
+  BackwardLayout b;
+  backward_layout(*T, L, !have_cache && want_dl, &b);
+  if (b.total > 0 && (!ws || ws_bytes < b.total)) return KP_ERR_WORKSPACE;
+  // outputs must not overlap inputs or the workspace
+  const size_t Tb = static_cast<size_t>(numel(*T)) * es;
+  const size_t Gb = static_cast<size_t>(numel(*G)) * es;
+  if (dT) {
+    const size_t db = static_cast<size_t>(numel(*dT)) * es;
+    if (overlaps(dT->data, db, T->data, Tb) || overlaps(dT->data, db, G->data, Gb) ||
+        overlaps(dT->data, db, ws, b.total) || overlaps(dT->data, db, cache, need_cache))
+      return KP_ERR_ALIAS;
+    for (int k = 0; k < d; ++k)
+      if (overlaps(dT->data, db, L[k]->data, matrix_span_bytes(*L[k]))) return KP_ERR_ALIAS;
+  }
+  if (dL) {
+    for (int k = 0; k < d; ++k) {
+      if (!dL[k]) continue;
+      const size_t lb = matrix_span_bytes(*dL[k]);
+      if (overlaps(dL[k]->data, lb, T->data, Tb) || overlaps(dL[k]->data, lb, G->data, Gb) ||
+          overlaps(dL[k]->data, lb, ws, b.total))
+        return KP_ERR_ALIAS;
+      for (int j = 0; j < d; ++j)
+        if (overlaps(dL[k]->data, lb, L[j]->data, matrix_span_bytes(*L[j]))) return KP_ERR_ALIAS;
+    }
+  }
+  const int form = form_of(prec, T->dtype);
+  char* wsb = static_cast<char*>(ws);
+
+  // Forward partials P_1..P_{d-1} (definition order), packed like the cache.
+  const void* Pk[KP_MAX_ORDER];
+  Pk[0] = T->data;
+  ChainPlan chain;
+  make_chain(*T, L, true, &chain);
+  if (want_dl && d > 1) {
+    const char* base = have_cache ? static_cast<const char*>(cache) : wsb + b.p_off;
+    size_t off = 0;
+    for (int k = 1; k < d; ++k) {
+      Pk[k] = base + off;
+      off += align_up(static_cast<size_t>(chain.size[k]) * es);
+    }
+    if (!have_cache) {
+      for (int k = 1; k < d; ++k) {
+        const ModeArgs a = mode_args(Pk[k - 1], const_cast<void*>(Pk[k]), chain.dims[k - 1], d,
+                                     k - 1, *L[k - 1], 0);
+        st = hip_status(launch_mode(form, a, tile_override(), stream));
+        if (st) return st;
+      }
+    }
+  }
+
+  // Reverse sweep: Q_d = G, Q_{mu-1} = Q_mu x_mu L_mu^T.
+  int last_needed = 1;  // smallest mu whose Q_mu is needed
+  if (!dT) {
+    last_needed = d + 1;
+    for (int k = 0; k < d; ++k)
+      if (dL && dL[k] && k + 1 < last_needed) last_needed = k + 1;
+  }
+  const void* Qmu = G->data;
+  int64_t qdims[KP_MAX_ORDER];  // dims of Q_mu
+  for (int k = 0; k < d; ++k) qdims[k] = L[k]->rows;
+  for (int mu = d; mu >= 1 && mu >= last_needed; --mu) {
+    const int k = mu - 1;
+    if (dL && dL[k]) {
+      int64_t Il = 1, Ir = 1;
+      for (int j = 0; j < k; ++j) Il *= qdims[j];
+      for (int j = k + 1; j < d; ++j) Ir *= qdims[j];
+      st = hip_status(launch_gram(T->dtype, Qmu, Pk[k], Il, L[k]->rows, L[k]->cols, Ir,
+                                  wsb + b.g_off, dL[k]->data, dL[k]->rs, dL[k]->cs, stream));
+      if (st) return st;
+    }
+    if (mu == 1 && !dT) break;
+    if (mu > last_needed || (mu == 1 && dT)) {
+      kp_matrix Lt = *L[k];
+      Lt.rows = L[k]->cols;
+      Lt.cols = L[k]->rows;
+      Lt.rs = L[k]->cs;
+      Lt.cs = L[k]->rs;
+      void* dst = (mu == 1) ? dT->data : wsb + b.q_off[(d - mu) & 1];
+      const ModeArgs a = mode_args(Qmu, dst, qdims, d, k, Lt, 0);
+      st = hip_status(launch_mode(form, a, tile_override(), stream));
+      if (st) return st;
+      Qmu = dst;
+      qdims[k] = L[k]->cols;
+    }
   }
   return KP_OK;
 }

@@ -13,4 +13,13 @@ int hip_status(hipError_t e);
 size_t elem_size(int dtype);
 size_t align_up(size_t x);
 
+// Factor-gradient contraction (gram_kernels.hip): dL(i,j) = sum_r Q(r,i) P(r,j)
+// over the fibers of the views Q (Il, n, Ir) and P (Il, m, Ir), written at
+// dL[i*rs + j*cs]; `part` is a workspace of gram_workspace() bytes.
+int64_t gram_splits(int64_t Il, int64_t n, int64_t m, int64_t Ir);
+size_t gram_workspace(int64_t Il, int64_t n, int64_t m, int64_t Ir, size_t esize);
+hipError_t launch_gram(int dtype, const void* Q, const void* P, int64_t Il, int64_t n, int64_t m,
+                       int64_t Ir, void* part, void* dL, int64_t rs, int64_t cs,
+                       hipStream_t stream);
+
 }  // namespace kp

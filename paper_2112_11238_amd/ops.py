@@ -153,6 +153,80 @@ def tucker(T, Ls, prec="native"):
     return _tucker_call(T, Ls, prec, False)[0]
 
 
+def tucker_backward(G, T, Ls, prec="native", cache=None, need_dT=True, need_dL=None):
+    """Gradient of <G, tucker(T, Ls)>: returns (dT, [dL_1, ..., dL_d]).
+
+    dT = G x_1 L_1^T ... x_d L_d^T, dL_mu = Q_mu^(mu) P_{mu-1}^(mu)^T (see
+    include/kp.h). ``cache`` is the forward cache returned by
+    ``tucker_with_cache`` (None: the partial products are recomputed).
+    ``need_dL`` is a list of booleans (default: all); skipped entries are None.
+    """
+    _check_device(G, T, *Ls)
+    d = T.dim()
+    if len(Ls) != d or any(L is None for L in Ls):
+        raise ValueError("the backward needs all d factors")
+    if need_dL is None:
+        need_dL = [True] * d
+    Tc, Gc = _canon(T), _canon(G)
+    dT = torch.empty_like(Tc) if need_dT else None
+    dLs = [torch.empty(L.shape, dtype=T.dtype, device=T.device) if need_dL[k] else None
+           for k, L in enumerate(Ls)]
+    td, gd = _tdesc(Tc, True), _tdesc(Gc, True)
+    mds = [_mdesc(L) for L in Ls][::-1]
+    dls = [None if x is None else _mdesc(x) for x in dLs][::-1]
+    arr, darr = _mlist(mds), _mlist(dls)
+    p = _prec(prec)
+    lb = lib()
+    ws_bytes = lb.kp_tucker_backward_workspace(ctypes.byref(td), arr, p)
+    ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=T.device)
+    dtd = _tdesc(dT, True) if dT is not None else None
+    cache_ptr = cache.data_ptr() if cache is not None else None
+    cache_bytes = cache.numel() if cache is not None else 0
+    st = lb.kp_tucker_backward(ctypes.byref(gd), ctypes.byref(td), arr, cache_ptr, cache_bytes,
+                               ctypes.byref(dtd) if dtd is not None else None, darr, p,
+                               ws.data_ptr(), ws_bytes, _stream())
+    check(st, "kp_tucker_backward")
+    return dT, dLs
+
+
+def tucker_with_cache(T, Ls, prec="native"):
+    """Tucker operator that also returns the forward cache of partial
+    products P_1..P_{d-1} (a uint8 device buffer) for tucker_backward."""
+    return _tucker_call(T, Ls, prec, True)
+
+
+class TuckerFunction(torch.autograd.Function):
+    """S = T x_1 L_1 ... x_d L_d with the hand-written backward.
+
+    forward(T, prec, cache_partials, *Ls); with cache_partials the forward
+    keeps P_1..P_{d-1} for the backward, otherwise they are recomputed."""
+
+    @staticmethod
+    def forward(ctx, T, prec, cache_partials, *Ls):
+        if cache_partials:
+            S, cache = tucker_with_cache(T, list(Ls), prec)
+        else:
+            S, cache = tucker(T, list(Ls), prec), None
+        ctx.prec = prec
+        ctx.cache = cache
+        ctx.save_for_backward(T, *Ls)
+        return S
+
+    @staticmethod
+    def backward(ctx, G):
+        T, *Ls = ctx.saved_tensors
+        need = ctx.needs_input_grad
+        dT, dLs = tucker_backward(G.contiguous(), T, Ls, ctx.prec, ctx.cache,
+                                  need_dT=need[0], need_dL=list(need[3:]))
+        ctx.cache = None
+        return (dT, None, None, *dLs)
+
+
+def tucker_autograd(T, Ls, prec="native", cache_partials=True):
+    """Differentiable Tucker operator (torch.autograd) over libkp's kernels."""
+    return TuckerFunction.apply(T, prec, cache_partials, *Ls)
+
+
 def force_tile(nb=0, fb=0, bk=0, occ=0):
     """Force the mode-kernel tile for later launches (nb=0 resets)."""
     check(lib().kp_force_tile(nb, fb, bk, occ), "kp_force_tile")
