@@ -146,12 +146,18 @@ int kp_tucker_backward(const kp_tensor* G, const kp_tensor* T,
                        size_t cache_bytes, kp_tensor* dT, kp_matrix* const* dL,
                        int prec, void* ws, size_t ws_bytes, hipStream_t stream);
 
-/* ---- exponential of a small matrix in FP64 (Sec. 3.3 factor build) ----------
- * E = exp(tau * A) for the n x n column-major FP64 matrix A (device memory),
- * n <= 256, by scaling and squaring with the degree-13 Pade approximant
- * (Higham 2005). E is n x n column-major. ws_bytes >= kp_expm_workspace(n). */
-size_t kp_expm_workspace(int64_t n);
-int kp_expm_f64(const double* A, int64_t n, double tau, double* E, void* ws,
+/* ---- exponential of small matrices in FP64 (Sec. 3.3 factor build) ----------
+ * E_k = exp(tau * A_k) for `count` n x n column-major FP64 matrices stored one
+ * after another in A (device memory); E receives them in the same layout.
+ * n <= 256. Scaling and squaring with the degree-13 diagonal Pade approximant
+ * (Higham 2005), all steps on the device (one workgroup per matrix), so the
+ * call never synchronises. ws_bytes >= kp_expm_workspace(n, count).
+ * Errors: KP_ERR_SHAPE (n < 0, n > 256, count < 0), KP_ERR_NULL,
+ * KP_ERR_VALUE (tau not finite), KP_ERR_WORKSPACE, KP_ERR_ALIAS (E overlaps
+ * A or the workspace). A singular Pade denominator (impossible for finite
+ * ||tau A||) would propagate Inf/NaN. */
+size_t kp_expm_workspace(int64_t n, int64_t count);
+int kp_expm_f64(const double* A, int64_t n, int64_t count, double tau, double* E, void* ws,
                 size_t ws_bytes, hipStream_t stream);
 
 /* ---- tuning ----------------------------------------------------------------

@@ -61,8 +61,9 @@ SIGNATURES = {
     "kp_tucker_backward_workspace": (_S, [_T, _MA, ctypes.c_int]),
     "kp_tucker_backward": (ctypes.c_int, [_T, _T, _MA, _V, _S, _T, _MA, ctypes.c_int,
                                           _V, _S, _V]),
-    "kp_expm_workspace": (_S, [ctypes.c_int64]),
-    "kp_expm_f64": (ctypes.c_int, [_V, ctypes.c_int64, ctypes.c_double, _V, _V, _S, _V]),
+    "kp_expm_workspace": (_S, [ctypes.c_int64, ctypes.c_int64]),
+    "kp_expm_f64": (ctypes.c_int, [_V, ctypes.c_int64, ctypes.c_int64, ctypes.c_double, _V, _V,
+                                   _S, _V]),
     "kp_force_tile": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     "kp_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "kp_version": (ctypes.c_int, []),

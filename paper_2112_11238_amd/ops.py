@@ -227,6 +227,31 @@ def tucker_autograd(T, Ls, prec="native", cache_partials=True):
     return TuckerFunction.apply(T, prec, cache_partials, *Ls)
 
 
+def expm(A, tau=1.0):
+    """exp(tau * A) in FP64 on the device for a square matrix A (n <= 256) or
+    a batch of them (shape (count, n, n)). Scaling and squaring with the
+    degree-13 Pade approximant, all in one launch (kp_expm_f64)."""
+    _check_device(A)
+    if A.dtype != torch.float64:
+        raise TypeError("expm runs in float64")
+    batched = A.dim() == 3
+    Ab = A if batched else A.unsqueeze(0)
+    if Ab.dim() != 3 or Ab.shape[1] != Ab.shape[2]:
+        raise ValueError("expects square matrices")
+    count, n = Ab.shape[0], Ab.shape[1]
+    # the library reads column-major matrices: pass A^T row-major = A col-major
+    Ac = Ab.transpose(1, 2).contiguous()
+    E = torch.empty_like(Ac)
+    lb = lib()
+    ws_bytes = lb.kp_expm_workspace(n, count)
+    ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=A.device)
+    st = lb.kp_expm_f64(Ac.data_ptr(), n, count, float(tau), E.data_ptr(), ws.data_ptr(),
+                        ws_bytes, _stream())
+    check(st, "kp_expm_f64")
+    E = E.transpose(1, 2)
+    return E if batched else E[0]
+
+
 def force_tile(nb=0, fb=0, bk=0, occ=0):
     """Force the mode-kernel tile for later launches (nb=0 resets)."""
     check(lib().kp_force_tile(nb, fb, bk, occ), "kp_force_tile")
