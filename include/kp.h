@@ -117,13 +117,17 @@ int kp_mump(const kp_tensor* T, const kp_matrix* L, int mu, kp_tensor* S,
  * n_1..n_d. A NULL L[k] is the identity (mode skipped, n_k = m_k).
  * The products are applied in an order chosen to minimise flops (the
  * operator does not depend on the order, Sec. 2); ties keep 1..d.
- * Intermediates live in the workspace `ws` (ws_bytes >= kp_tucker_workspace).
+ * Intermediates live in the workspace `ws` (ws_bytes >= kp_tucker_workspace);
+ * with a cache they are written into the cache instead and ws may be NULL.
  * If `cache` is non-NULL it receives the forward partial products
  * P_k = T x_1 L_1 ... x_k L_k for k = 1..d-1 in definition order, packed one
  * after another as column-major tensors (cache_bytes >= kp_tucker_cache_size);
  * kp_tucker_backward can reuse them. Requesting the cache forces the
  * definition order 1..d. */
 size_t kp_tucker_workspace(const kp_tensor* T, const kp_matrix* const* L, int prec);
+/* The order kp_tucker applies the non-identity factors in (without a cache):
+ * order[0..*count-1] receives 1-based modes. Host-only query. */
+int kp_tucker_order(const kp_tensor* T, const kp_matrix* const* L, int* order, int* count);
 size_t kp_tucker_cache_size(const kp_tensor* T, const kp_matrix* const* L);
 int kp_tucker(const kp_tensor* T, const kp_matrix* const* L, kp_tensor* S,
               int prec, void* ws, size_t ws_bytes,

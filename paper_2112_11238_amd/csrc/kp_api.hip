@@ -293,16 +293,23 @@ int kp_mump(const kp_tensor* T, const kp_matrix* L, int mu, kp_tensor* S, int pr
 
 size_t kp_tucker_workspace(const kp_tensor* T, const kp_matrix* const* L, int prec) {
   if (validate_tucker_args(T, L, prec)) return 0;
+  // exactly what kp_tucker checks on its workspace path (no cache)
   ChainPlan p;
   make_chain(*T, L, false, &p);
   size_t off1, total;
   chain_ws(p, elem_size(T->dtype), &off1, &total);
-  // the definition-order chain (used when a cache is requested) may differ
-  ChainPlan q;
-  make_chain(*T, L, true, &q);
-  size_t off1q, totalq;
-  chain_ws(q, elem_size(T->dtype), &off1q, &totalq);
-  return total > totalq ? total : totalq;
+  return total;
+}
+
+int kp_tucker_order(const kp_tensor* T, const kp_matrix* const* L, int* order, int* count) {
+  const int st = validate_tucker_args(T, L, KP_PREC_NATIVE);
+  if (st) return st;
+  if (!order || !count) return KP_ERR_NULL;
+  ChainPlan p;
+  make_chain(*T, L, false, &p);
+  for (int s = 0; s < p.count; ++s) order[s] = p.order[s] + 1;
+  *count = p.count;
+  return KP_OK;
 }
 
 size_t kp_tucker_cache_size(const kp_tensor* T, const kp_matrix* const* L) {

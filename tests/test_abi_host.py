@@ -1,0 +1,257 @@
+"""Host-side checks of the C-ABI (no GPU needed, no kernel is launched):
+exported symbols, struct layout, argument validation, workspace queries and
+the mode-order planner."""
+import ctypes
+import itertools
+import os
+import re
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+import kp_workloads
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "kp.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2112_11238_amd import _lib
+    return _lib
+
+
+@pytest.fixture(scope="module")
+def lib(L):
+    return L.load()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(kp_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(lib, L):
+    names = declared_functions()
+    assert len(names) >= 12
+    for name in names:
+        assert hasattr(lib, name), name
+        assert name in L.SIGNATURES, f"binding lacks a prototype for {name}"
+
+
+def test_struct_layout_matches_header(L):
+    gcc = shutil.which("gcc")
+    if not gcc or not os.path.exists("/opt/rocm/include/hip/hip_runtime_api.h"):
+        pytest.skip("gcc or HIP headers missing")
+    exe = os.path.join(ROOT, "tests", ".abi_layout_bin")
+    r = subprocess.run([gcc, "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"),
+                        "-I", "/opt/rocm/include", os.path.join(ROOT, "tests", "abi_layout.c"),
+                        "-o", exe], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    out = subprocess.run([exe], capture_output=True, text=True).stdout.split("\n")
+    os.remove(exe)
+    t = out[0].split()
+    assert int(t[1]) == ctypes.sizeof(L.KpTensor)
+    for name, off in zip(t[2::2], t[3::2]):
+        assert getattr(L.KpTensor, name).offset == int(off), name
+    mline = out[1].split()
+    assert int(mline[1]) == ctypes.sizeof(L.KpMatrix)
+    for name, off in zip(mline[2::2], mline[3::2]):
+        assert getattr(L.KpMatrix, name).offset == int(off), name
+    codes = [int(x) for x in out[2].split()[1:]]
+    assert codes == sorted(L.STATUS, reverse=True)
+    p = out[3].split()
+    assert [int(p[1]), int(p[2]), int(p[3])] == [L.KP_PREC_NATIVE, L.KP_PREC_BF16X3,
+                                                 L.KP_PREC_BF16X6]
+    assert [int(p[5]), int(p[6]), int(p[8])] == [L.KP_F64, L.KP_F32, L.KP_MAX_ORDER]
+
+
+def test_strerror_and_version(lib, L):
+    assert lib.kp_version() == 100
+    for code in L.STATUS:
+        assert lib.kp_strerror(code)
+    assert lib.kp_strerror(12345) == b"unknown status"
+
+
+FAKE = 0x10000  # a non-null address; never dereferenced: validation fails first
+
+
+def _gpu_visible():
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:  # pragma: no cover
+        return False
+
+
+# The argument-error tests hand the library fake device addresses that its
+# host-side validation must reject before any launch. They run only where no
+# GPU is visible, so that a validation bug can never reach a kernel.
+no_device = pytest.mark.skipif(_gpu_visible(), reason="fake-address tests run without a GPU")
+
+
+def tensor(L, dims, dtype=0, data=FAKE):
+    t = L.KpTensor()
+    t.d = len(dims)
+    t.dtype = dtype
+    for k, v in enumerate(dims[:8]):
+        t.dims[k] = v
+    t.data = data
+    return t
+
+
+def matrix(L, rows, cols, dtype=0, data=FAKE + 0x100000):
+    mtx = L.KpMatrix()
+    mtx.rows, mtx.cols = rows, cols
+    mtx.rs, mtx.cs = cols, 1
+    mtx.dtype = dtype
+    mtx.data = data
+    return mtx
+
+
+def mlist(L, ms):
+    arr = (ctypes.POINTER(L.KpMatrix) * len(ms))()
+    for k, x in enumerate(ms):
+        arr[k] = ctypes.pointer(x) if x is not None else None
+    return arr
+
+
+@no_device
+def test_mump_argument_errors(lib, L):
+    T = tensor(L, [4, 5, 6])
+    S = tensor(L, [4, 7, 6], data=FAKE + 0x200000)
+    M = matrix(L, 7, 5)
+    call = lambda t, m, mu, s, prec=0: lib.kp_mump(t, m, mu, s, prec, 0, None)
+    assert call(None, ctypes.byref(M), 2, ctypes.byref(S)) == -1
+    assert call(ctypes.byref(T), None, 2, ctypes.byref(S)) == -1
+    assert call(ctypes.byref(tensor(L, [])), ctypes.byref(M), 1, ctypes.byref(S)) == -2
+    assert call(ctypes.byref(tensor(L, [2] * 9)), ctypes.byref(M), 1, ctypes.byref(S)) == -2
+    assert call(ctypes.byref(T), ctypes.byref(M), 0, ctypes.byref(S)) == -3
+    assert call(ctypes.byref(T), ctypes.byref(M), 4, ctypes.byref(S)) == -3
+    assert call(ctypes.byref(T), ctypes.byref(matrix(L, 7, 6)), 2, ctypes.byref(S)) == -4
+    assert call(ctypes.byref(T), ctypes.byref(M), 2, ctypes.byref(tensor(L, [4, 8, 6]))) == -4
+    assert call(ctypes.byref(T), ctypes.byref(matrix(L, 7, 5, dtype=1)), 2,
+                ctypes.byref(S)) == -5
+    # BF16 split forms need FP32 data
+    assert call(ctypes.byref(T), ctypes.byref(M), 2, ctypes.byref(S), prec=3) == -5
+    assert call(ctypes.byref(T), ctypes.byref(M), 2, ctypes.byref(S), prec=5) == -5
+    # output overlapping the input
+    S_alias = tensor(L, [4, 7, 6], data=FAKE + 8)
+    assert call(ctypes.byref(T), ctypes.byref(M), 2, ctypes.byref(S_alias)) == -6
+    # NULL data with a non-empty tensor
+    assert call(ctypes.byref(tensor(L, [4, 5, 6], data=None)), ctypes.byref(M), 2,
+                ctypes.byref(S)) == -1
+
+
+@no_device
+def test_tucker_argument_errors(lib, L):
+    T = tensor(L, [4, 5, 6], dtype=1)
+    Ms = [matrix(L, 3, 4, 1), matrix(L, 2, 5, 1), matrix(L, 5, 6, 1)]
+    S = tensor(L, [3, 2, 5], dtype=1, data=FAKE + 0x300000)
+    arr = mlist(L, Ms)
+    need = lib.kp_tucker_workspace(ctypes.byref(T), arr, 0)
+    assert need > 0
+    # workspace missing / too small is reported before anything is launched
+    assert lib.kp_tucker(ctypes.byref(T), arr, ctypes.byref(S), 0, None, 0, None, 0, None) == -7
+    assert lib.kp_tucker(ctypes.byref(T), arr, ctypes.byref(S), 0, FAKE + 0x900000, need - 1,
+                         None, 0, None) == -7
+    bad = mlist(L, [matrix(L, 3, 4, 1), matrix(L, 2, 6, 1), matrix(L, 5, 6, 1)])
+    assert lib.kp_tucker(ctypes.byref(T), bad, ctypes.byref(S), 0, None, 0, None, 0, None) == -4
+    assert lib.kp_tucker(ctypes.byref(T), arr, ctypes.byref(tensor(L, [3, 2, 4], dtype=1)), 0,
+                         None, 0, None, 0, None) == -4
+    # cache smaller than required
+    cb = lib.kp_tucker_cache_size(ctypes.byref(T), arr)
+    assert cb > 0
+    assert lib.kp_tucker(ctypes.byref(T), arr, ctypes.byref(S), 0, None, 0, FAKE + 0x900000,
+                         cb - 1, None) == -7
+
+
+@no_device
+def test_backward_argument_errors(lib, L):
+    T = tensor(L, [4, 5], dtype=0)
+    G = tensor(L, [3, 2], dtype=0, data=FAKE + 0x400000)
+    Ms = mlist(L, [matrix(L, 3, 4), matrix(L, 2, 5)])
+    need = lib.kp_tucker_backward_workspace(ctypes.byref(T), Ms, 0)
+    assert need > 0
+    dT = tensor(L, [4, 5], data=FAKE + 0x500000)
+    assert lib.kp_tucker_backward(ctypes.byref(G), ctypes.byref(T), Ms, None, 0,
+                                  ctypes.byref(dT), None, 0, None, 0, None) == -7
+    with_null = mlist(L, [matrix(L, 3, 4), None])
+    assert lib.kp_tucker_backward(ctypes.byref(G), ctypes.byref(T), with_null, None, 0,
+                                  ctypes.byref(dT), None, 0, None, 0, None) == -1
+    assert lib.kp_tucker_backward(ctypes.byref(tensor(L, [3, 3], data=FAKE + 0x400000)),
+                                  ctypes.byref(T), Ms, None, 0, ctypes.byref(dT), None, 0,
+                                  None, 0, None) == -4
+    # dT aliasing T
+    assert lib.kp_tucker_backward(ctypes.byref(G), ctypes.byref(T), Ms, None, 0,
+                                  ctypes.byref(tensor(L, [4, 5])), None, 0,
+                                  FAKE + 0x900000, need, None) == -6
+
+
+@no_device
+def test_expm_argument_errors(lib):
+    ws = lib.kp_expm_workspace(128, 3)
+    assert ws == 8 * 128 * 128 * 3 * 8
+    assert lib.kp_expm_f64(FAKE, 300, 1, 1.0, FAKE * 2, FAKE * 4, 10 ** 9, None) == -4
+    assert lib.kp_expm_f64(None, 4, 1, 1.0, FAKE, FAKE * 4, 10 ** 6, None) == -1
+    assert lib.kp_expm_f64(FAKE, 4, 1, float("nan"), FAKE * 2, FAKE * 4, 10 ** 6, None) == -9
+    assert lib.kp_expm_f64(FAKE, 4, 1, 1.0, FAKE * 2, FAKE * 4, 10, None) == -7
+    assert lib.kp_expm_f64(FAKE, 4, 1, 1.0, FAKE + 8, FAKE * 4, 10 ** 6, None) == -6
+    assert lib.kp_expm_f64(FAKE, 0, 1, 1.0, FAKE * 2, None, 0, None) == 0
+
+
+def test_force_tile_argument_errors(lib):
+    assert lib.kp_force_tile(4, 0, 16, 0) == -9
+    assert lib.kp_force_tile(0, 0, 0, 0) == 0
+
+
+def test_workspace_sizes(lib, L):
+    # cube200 FP64: two ping-pong buffers of one 8M-entry intermediate each
+    T = tensor(L, [200, 200, 200])
+    arr = mlist(L, [matrix(L, 200, 200)] * 3)
+    assert lib.kp_tucker_workspace(ctypes.byref(T), arr, 0) == 2 * 200 ** 3 * 8
+    assert lib.kp_tucker_cache_size(ctypes.byref(T), arr) == 2 * 200 ** 3 * 8
+    # interp6d FP32: cache holds P_1..P_5
+    T6 = tensor(L, [16] * 6, dtype=1)
+    arr6 = mlist(L, [matrix(L, 24, 16, 1)] * 6)
+    want = sum(((24 ** k) * 16 ** (6 - k) * 4 + 255) // 256 * 256 for k in range(1, 6))
+    assert lib.kp_tucker_cache_size(ctypes.byref(T6), arr6) == want
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_planned_order_minimises_flops(lib, L, seed):
+    rng = np.random.default_rng(900 + seed)
+    d = int(rng.integers(2, 6))
+    m = [int(x) for x in rng.integers(1, 40, size=d)]
+    n = [int(x) for x in rng.integers(1, 40, size=d)]
+    T = tensor(L, m)
+    arr = mlist(L, [matrix(L, n[k], m[k]) for k in range(d)])
+    order = (ctypes.c_int * 8)()
+    cnt = ctypes.c_int()
+    assert lib.kp_tucker_order(ctypes.byref(T), arr, order, ctypes.byref(cnt)) == 0
+    got = [order[k] for k in range(cnt.value)]
+    assert sorted(got) == list(range(1, d + 1))
+    best = min(kp_workloads.tucker_flops(m, n, p)
+               for p in itertools.permutations(range(1, d + 1)))
+    assert kp_workloads.tucker_flops(m, n, got) == best
+
+
+def test_planned_order_skips_identity_factors(lib, L):
+    T = tensor(L, [5, 6, 7])
+    arr = mlist(L, [None, matrix(L, 3, 6), None])
+    order = (ctypes.c_int * 8)()
+    cnt = ctypes.c_int()
+    assert lib.kp_tucker_order(ctypes.byref(T), arr, order, ctypes.byref(cnt)) == 0
+    assert cnt.value == 1 and order[0] == 2
+
+
+def test_binding_refuses_cpu_tensors():
+    import torch
+    import paper_2112_11238_amd as kp
+    with pytest.raises(ValueError, match="GPU tensors only"):
+        kp.tucker(torch.zeros(3, 3, dtype=torch.float64), [None, None])
+    with pytest.raises(ValueError, match="GPU tensors only"):
+        kp.mump(torch.zeros(3, 3), torch.zeros(2, 3), 1)
