@@ -1,0 +1,120 @@
+"""Full-size parity of the Tucker operator on every workload, in the launch
+configuration the benchmark times (default tiles, kp_tucker)."""
+import numpy as np
+import pytest
+import torch
+
+import kp_workloads
+import oracle
+from gpu_util import cast64, chain_bound, rel_max, say, to_dev, unit_error
+
+pytestmark = pytest.mark.gpu
+
+FORMS = [("f64", "native"), ("f32", "native"), ("f32", "bf16x3"), ("f32", "bf16x6")]
+DT = {"f64": torch.float64, "f32": torch.float32}
+# precision targets of the method's forms (max-norm relative error)
+TARGET = {("f64", "native"): 1e-13, ("f32", "native"): 1e-6, ("f32", "bf16x6"): 1e-6}
+
+
+@pytest.fixture(scope="module")
+def kp():
+    import paper_2112_11238_amd as kp
+    return kp
+
+
+def run(kp, T, Ls, dt, prec):
+    S = kp.tucker(to_dev(T, DT[dt]), [to_dev(L, DT[dt]) for L in Ls], prec=prec)
+    torch.cuda.synchronize()
+    return S
+
+
+@pytest.mark.parametrize("dt,prec", FORMS)
+def test_small2d(kp, dt, prec):
+    T, Ls = kp_workloads.small2d()
+    say("small2d", dt, prec)
+    got = run(kp, T, Ls, dt, prec).double().cpu().numpy()
+    T64, L64 = cast64(T, DT[dt]), [cast64(L, DT[dt]) for L in Ls]
+    ref = oracle.tucker(T64, L64)
+    assert np.all(np.abs(got - ref) <= chain_bound(T64, L64, prec, DT[dt]))
+    if (dt, prec) in TARGET:
+        assert rel_max(got, ref) <= TARGET[(dt, prec)]
+
+
+@pytest.mark.parametrize("dt,prec", FORMS)
+def test_cube200_full(kp, dt, prec):
+    T, Ls = kp_workloads.cube200()
+    say("cube200", dt, prec)
+    got = run(kp, T, Ls, dt, prec).double().cpu().numpy()
+    T64, L64 = cast64(T, DT[dt]), [cast64(L, DT[dt]) for L in Ls]
+    ref = oracle.tucker(T64, L64)
+    err = rel_max(got, ref)
+    say("rel err", err)
+    assert np.all(np.abs(got - ref) <= chain_bound(T64, L64, prec, DT[dt]))
+    if (dt, prec) in TARGET:
+        assert err <= TARGET[(dt, prec)]
+
+
+@pytest.mark.parametrize("prec", ["native", "bf16x3", "bf16x6"])
+def test_interp6d_sampled_entries(kp, prec):
+    T, Ls = kp_workloads.interp6d()
+    say("interp6d sampled", prec)
+    S = run(kp, T, Ls, "f32", prec)
+    T64 = cast64(T, torch.float32)
+    L64 = [cast64(L, torch.float32) for L in Ls]
+    rng = np.random.default_rng(77)
+    idx = [tuple(int(v) for v in rng.integers(0, 24, size=6)) for _ in range(120)]
+    idx += [(0,) * 6, (23,) * 6, (0, 23, 0, 23, 0, 23)]
+    Sc = S.cpu()
+    absT = np.abs(T64)
+    absL = [np.abs(L) for L in L64]
+    coef = 2 * 6 * {"native": 18 * 2.0 ** -24, "bf16x3": 3 * 2.0 ** -16 + 18 * 2.0 ** -24,
+                    "bf16x6": 6 * 2.0 ** -24 + 18 * 2.0 ** -24}[prec]
+    for i in idx:
+        ref = oracle.tucker_entry(T64, L64, i)
+        bound = coef * oracle.tucker_entry(absT, absL, i)
+        assert abs(float(Sc[i]) - ref) <= bound, i
+
+
+@pytest.mark.parametrize("prec", ["native", "bf16x6"])
+def test_interp6d_polynomial_reproduction_full(kp, prec):
+    # T samples a separable polynomial of degree <= 15 per variable at the 16
+    # Chebyshev nodes; the Lagrange factors reproduce it exactly on the 24
+    # uniform points, so S equals the polynomial on the full 24^6 grid.
+    _, Ls = kp_workloads.interp6d()
+    xi = oracle.chebyshev_nodes(16)
+    x = np.linspace(-1, 1, 24)
+    rng = np.random.default_rng(78)
+    coefs = rng.standard_normal((6, 16)) / np.arange(1, 17)
+    fn = [np.polyval(c, xi) for c in coefs]
+    fx = [np.polyval(c, x) for c in coefs]
+    T = fn[0]
+    for k in range(1, 6):
+        T = np.multiply.outer(T, fn[k])
+    say("interp6d polynomial reproduction", prec)
+    S = run(kp, T, Ls, "f32", prec)
+    P = torch.tensor(fx[0], dtype=torch.float64, device="cuda")
+    for k in range(1, 6):
+        P = torch.multiply(P.unsqueeze(-1), torch.tensor(fx[k], dtype=torch.float64,
+                                                           device="cuda"))
+    err = float((S.double() - P).abs().max() / P.abs().max())
+    say("rel err", err)
+    # FP32 inputs and factors: relative error of a few units of 2^-24 per mode
+    assert err < 2e-5
+
+
+@pytest.mark.parametrize("prec", ["native", "bf16x3", "bf16x6"])
+def test_batch64_each_tensor(kp, prec):
+    sizes, items = kp_workloads.batch64()
+    say("batch64 per tensor", prec)
+    for k, (T, Ls) in enumerate(items):
+        got = run(kp, T, Ls, "f32", prec).double().cpu().numpy()
+        T64, L64 = cast64(T, torch.float32), [cast64(L, torch.float32) for L in Ls]
+        if k % 8 == 0:
+            ref = oracle.tucker(T64, L64)
+            assert np.all(np.abs(got - ref) <= chain_bound(T64, L64, prec, torch.float32)), k
+        else:
+            coef = 2 * sum(unit_error(prec, torch.float32, int(s)) for s in sizes[k])
+            for i in [tuple(int(s) // 2 for s in sizes[k]), tuple(int(s) - 1 for s in sizes[k])]:
+                ref = oracle.tucker_entry(T64, L64, i)
+                bnd = coef * oracle.tucker_entry(np.abs(T64), [np.abs(L) for L in L64], i)
+                assert abs(got[i] - ref) <= bnd, (k, i)
