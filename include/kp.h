@@ -150,6 +150,49 @@ int kp_tucker_backward(const kp_tensor* G, const kp_tensor* T,
                        size_t cache_bytes, kp_tensor* dT, kp_matrix* const* dL,
                        int prec, void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* ---- batched Tucker operator: persistent launches per dependency level -----
+ * `count` independent problems of any orders and sizes (same dtype), each a
+ * Tucker operator in definition order (Sec. 2) and optionally its gradient.
+ * All tiles of all problems that sit at the same dependency level (the
+ * forward product of mode s, a factor-gradient partial sum, ...) run in ONE
+ * persistent launch; consecutive levels are consecutive launches on
+ * `stream`, so no workgroup waits for another. A forward pass of order-d
+ * problems takes d launches, forward plus backward about 2d + 2; a HIP graph
+ * capturing kp_tucker_batched replays the whole batch.
+ * Per problem: S = T x_1 L[0] ... x_d L[d-1] (no identity factors here).
+ * If G.data != NULL the backward runs too: dT (if dT.data != NULL) and every
+ * dL[k] with dL[k].data != NULL, as kp_tucker_backward defines them; the
+ * forward partial products are kept in the workspace for it.
+ * Each problem's tensors must stay below 2^31 bytes.
+ *
+ * Use: (1) ws_bytes = kp_batch_workspace(), plan_bytes = kp_batch_plan_bytes();
+ * (2) kp_batch_plan() writes the plan into HOST memory `plan`, with every
+ *     device address (inputs, outputs, intermediates in `ws`) resolved;
+ * (3) the caller copies the plan bytes to device memory `plan_dev`;
+ * (4) kp_tucker_batched(plan_dev, plan, ws, ...) enqueues the launches; it can
+ *     be called (or graph-replayed) any number of times while the buffers stay
+ *     valid. Calls that share `ws` must not overlap in time.
+ * Tile shapes per mode product come from the tuning table (kp_tune_set) or
+ * the built-in defaults, restricted to the variants the executor carries.
+ * Errors: KP_ERR_NULL, KP_ERR_ORDER, KP_ERR_DTYPE, KP_ERR_SHAPE (mismatched
+ * sizes, NULL or identity factors, a tensor of 2^31 bytes or more),
+ * KP_ERR_WORKSPACE (ws or plan too small, or ws not the planned one),
+ * KP_ERR_VALUE (count < 0, plan bytes not a plan). */
+typedef struct {
+  kp_tensor T, S;
+  kp_matrix L[KP_MAX_ORDER];
+  kp_tensor G, dT;
+  kp_matrix dL[KP_MAX_ORDER];
+} kp_batch_item;
+
+size_t kp_batch_workspace(int count, const kp_batch_item* items, int prec);
+size_t kp_batch_plan_bytes(int count, const kp_batch_item* items, int prec);
+int kp_batch_plan(int count, const kp_batch_item* items, int prec, void* ws, size_t ws_bytes,
+                  void* plan, size_t plan_bytes);
+int kp_batch_info(const void* plan, int64_t* ntasks, int* nstages, int* nlevels);
+int kp_tucker_batched(const void* plan_dev, const void* plan, void* ws, size_t ws_bytes,
+                      hipStream_t stream);
+
 /* ---- exponential of small matrices in FP64 (Sec. 3.3 factor build) ----------
  * E_k = exp(tau * A_k) for `count` n x n column-major FP64 matrices stored one
  * after another in A (device memory); E receives them in the same layout.

@@ -6,7 +6,7 @@ hand-written HIP kernels behind the C-ABI of include/kp.h (libkp.so), with a
 thin torch binding (ops) that only marshals arguments.
 """
 from .ops import (mump, tucker, tucker_with_cache, tucker_backward,  # noqa: F401
-                  tucker_autograd, TuckerFunction, expm, force_tile)
+                  tucker_autograd, TuckerFunction, expm, BatchedTucker, force_tile)
 
 __all__ = ["mump", "tucker", "tucker_with_cache", "tucker_backward", "tucker_autograd",
-           "TuckerFunction", "expm", "force_tile"]
+           "TuckerFunction", "expm", "BatchedTucker", "force_tile"]

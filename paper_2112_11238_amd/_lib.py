@@ -38,6 +38,11 @@ class KpMatrix(ctypes.Structure):
                 ("data", ctypes.c_void_p)]
 
 
+class KpBatchItem(ctypes.Structure):
+    _fields_ = [("T", KpTensor), ("S", KpTensor), ("L", KpMatrix * KP_MAX_ORDER),
+                ("G", KpTensor), ("dT", KpTensor), ("dL", KpMatrix * KP_MAX_ORDER)]
+
+
 class KpError(RuntimeError):
     def __init__(self, status, where):
         self.status = status
@@ -65,6 +70,11 @@ SIGNATURES = {
     "kp_expm_workspace": (_S, [ctypes.c_int64, ctypes.c_int64]),
     "kp_expm_f64": (ctypes.c_int, [_V, ctypes.c_int64, ctypes.c_int64, ctypes.c_double, _V, _V,
                                    _S, _V]),
+    "kp_batch_workspace": (_S, [ctypes.c_int, P(KpBatchItem), ctypes.c_int]),
+    "kp_batch_plan_bytes": (_S, [ctypes.c_int, P(KpBatchItem), ctypes.c_int]),
+    "kp_batch_plan": (ctypes.c_int, [ctypes.c_int, P(KpBatchItem), ctypes.c_int, _V, _S, _V, _S]),
+    "kp_batch_info": (ctypes.c_int, [_V, P(ctypes.c_int64), P(ctypes.c_int), P(ctypes.c_int)]),
+    "kp_tucker_batched": (ctypes.c_int, [_V, _V, _V, _S, _V]),
     "kp_force_tile": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     "kp_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "kp_version": (ctypes.c_int, []),

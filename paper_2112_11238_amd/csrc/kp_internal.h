@@ -10,6 +10,10 @@ namespace kp {
 const ModeTile* tile_override();
 
 int hip_status(hipError_t e);
+// Three-index view arguments for the product of mode mu0 (0-based) of a
+// column-major tensor with sizes dims[0..d-1] (kp_api.hip).
+ModeArgs mode_args(const void* X, void* Y, const int64_t* dims, int d, int mu0,
+                   const kp_matrix& L, int accumulate);
 size_t elem_size(int dtype);
 size_t align_up(size_t x);
 

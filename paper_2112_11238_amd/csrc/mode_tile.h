@@ -1,0 +1,379 @@
+// Device-side tile of the mu-mode product for gfx950 (Sec. 2, Definition of
+// the mu-mode product), shared by the standalone mode kernels and the batched
+// persistent executor. The input is read in place as the (Il, m, Ir) view of
+// the column-major tensor; see mode_kernels.hip for the layouts and forms.
+#pragma once
+
+#include <hip/hip_bf16.h>
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "kp_common.h"
+
+namespace kp {
+namespace tile {
+
+constexpr int kThreads = 256;  // threads per workgroup (4 waves)
+
+// ---------------------------------------------------------------------------
+// MFMA operand layouts (checked on the device):
+//   16x16x4 (f64, f32): lane l feeds A[l%16][l/16] and B[l/16][l%16];
+//     accumulator item v of lane l is D[4v + l/16][l%16] for FP64 and
+//     D[4(l/16) + v][l%16] for FP32.
+//   16x16x32 bf16: lane l feeds A[l%16][8(l/16) .. +7] and
+//     B[8(l/16) .. +7][l%16]; item v of lane l is D[4(l/16) + v][l%16].
+// ---------------------------------------------------------------------------
+// Offset of fiber r = a + Il*b of a (Il, len, Ir) view: a + Il*len*b.
+__device__ __forceinline__ int64_t fiber_offset(int64_t r, int64_t Il, int64_t len) {
+  const int64_t b = r / Il;
+  return (r - b * Il) + Il * len * b;
+}
+
+// Round-to-nearest-even split of x into P bf16 terms: x1 = bf16(x),
+// x2 = bf16(x - x1), x3 = bf16(x - x1 - x2). Each difference is exact in FP32.
+template <int P>
+__device__ __forceinline__ void split_bf16(float x, __bf16 (&o)[P]) {
+  float r = x;
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    const __bf16 h = static_cast<__bf16>(r);
+    o[p] = h;
+    r = r - static_cast<float>(h);
+  }
+}
+
+// Per-form constants. The LDS tiles hold rows (an n index or a fiber) whose
+// k values are contiguous; every lane reads 16 bytes = KV consecutive k of
+// one row. Because the contraction is a plain sum over k, lane group
+// g = lane/16 may own k values [KV*g, KV*g + KV) of each macro step of
+// MK = 4*KV values: MFMA step s then pairs A[row][KV*g + s] with
+// B[KV*g + s][col] in every lane group, the same k on both operands.
+template <int FORM>
+struct FormT;
+
+template <>
+struct FormT<FORM_F64> {
+  using G = double;   // global element
+  using S = double;   // LDS element
+  static constexpr int P = 1, KV = 2, MK = 8;
+  using acc_t = d4_t;
+  static __device__ __forceinline__ int row(int l, int v) { return 4 * v + (l >> 4); }
+};
+template <>
+struct FormT<FORM_F32> {
+  using G = float;
+  using S = float;
+  static constexpr int P = 1, KV = 4, MK = 16;
+  using acc_t = f4_t;
+  static __device__ __forceinline__ int row(int l, int v) { return 4 * (l >> 4) + v; }
+};
+template <int FORM>
+struct FormBf16 {
+  using G = float;
+  using S = __bf16;
+  static constexpr int P = FORM == FORM_BF16X3 ? 2 : 3, KV = 8, MK = 32;
+  using acc_t = f4_t;
+  static __device__ __forceinline__ int row(int l, int v) { return 4 * (l >> 4) + v; }
+};
+template <>
+struct FormT<FORM_BF16X3> : FormBf16<FORM_BF16X3> {};
+template <>
+struct FormT<FORM_BF16X6> : FormBf16<FORM_BF16X6> {};
+
+template <int FORM>
+using Frag = typename std::conditional<FORM == FORM_F64, d2_t,
+             typename std::conditional<FORM == FORM_F32, f4v_t, bf16x8_t>::type>::type;
+
+// One macro step of MFMAs for one (row block, column block) pair.
+// A: KV k values of the MFMA row operand (per plane), B: same for the column
+// operand. hi/lo: accumulators (lo is unused by the native forms).
+template <int FORM>
+__device__ __forceinline__ void macro_step(const Frag<FORM> (&A)[FormT<FORM>::P],
+                                           const Frag<FORM> (&B)[FormT<FORM>::P],
+                                           typename FormT<FORM>::acc_t& hi,
+                                           typename FormT<FORM>::acc_t& lo) {
+  if constexpr (FORM == FORM_F64) {
+    hi = __builtin_amdgcn_mfma_f64_16x16x4f64(A[0][0], B[0][0], hi, 0, 0, 0);
+    hi = __builtin_amdgcn_mfma_f64_16x16x4f64(A[0][1], B[0][1], hi, 0, 0, 0);
+    (void)lo;
+  } else if constexpr (FORM == FORM_F32) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+      hi = __builtin_amdgcn_mfma_f32_16x16x4f32(A[0][s], B[0][s], hi, 0, 0, 0);
+    (void)lo;
+  } else {
+    // correction products (smallest first) into lo, the leading one into hi
+    if constexpr (FORM == FORM_BF16X6) {
+      lo = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[0], B[2], lo, 0, 0, 0);
+      lo = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[1], B[1], lo, 0, 0, 0);
+      lo = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[2], B[0], lo, 0, 0, 0);
+    }
+    lo = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[0], B[1], lo, 0, 0, 0);
+    lo = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[1], B[0], lo, 0, 0, 0);
+    hi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[0], B[0], hi, 0, 0, 0);
+  }
+}
+
+// NB: 16-blocks along n per workgroup (every wave covers all of them).
+// FB: 16-blocks of fibers per wave; 4 waves split the fibers, so a workgroup
+//     covers 64*FB fibers.
+// BK: k values staged through LDS per chunk (double buffered, one barrier
+//     per chunk). OCC: waves per SIMD the register budget is sized for.
+// LDS bytes one tile of a variant needs (double-buffered L and X tiles).
+template <int FORM, int NB, int FB, int BK>
+constexpr size_t mode_lds_bytes() {
+  using FT = FormT<FORM>;
+  constexpr int LDK = BK + 16 / sizeof(typename FT::S);
+  return 2 * FT::P * (16 * NB + 64 * FB) * LDK * sizeof(typename FT::S);
+}
+
+// One output tile (fiber block bx, n block by) of a mu-mode product,
+// computed by the 256 threads of a workgroup; `lds` holds
+// mode_lds_bytes<...>() bytes, 16-byte aligned.
+template <int FORM, int NB, int FB, int BK, bool INNER>
+__device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t bx, int64_t by,
+                                          char* __restrict__ lds) {
+  using FT = FormT<FORM>;
+  using G = typename FT::G;
+  using SE = typename FT::S;
+  using acc_t = typename FT::acc_t;
+  using FragT = Frag<FORM>;
+  constexpr int P = FT::P, KV = FT::KV, MK = FT::MK;
+  constexpr bool SPLIT = FORM == FORM_BF16X3 || FORM == FORM_BF16X6;
+  constexpr int BN = 16 * NB;
+  constexpr int BF = 64 * FB;
+  constexpr int KG = BK / KV;                 // k groups per row and chunk
+  constexpr int LDK = BK + 16 / sizeof(SE);   // row stride: +16 bytes
+  constexpr int XT = (BF * KG + kThreads - 1) / kThreads;  // X tasks / thread
+  constexpr int LT = (BN * KG + kThreads - 1) / kThreads;  // L tasks / thread
+  constexpr int QB = INNER ? NB : FB;  // MFMA row blocks
+  constexpr int PB = INNER ? FB : NB;  // MFMA column blocks
+  static_assert(BK % MK == 0, "BK must be a multiple of the macro step");
+  static_assert(!INNER || kThreads % BF == 0, "BF must divide the block size");
+
+  typedef SE LTile[P][BN][LDK];
+  typedef SE XTile[P][BF][LDK];
+  LTile* sL = reinterpret_cast<LTile*>(lds);
+  XTile* sX = reinterpret_cast<XTile*>(lds + 2 * sizeof(LTile));
+
+  const G* __restrict__ X = static_cast<const G*>(a.X);
+  const G* __restrict__ L = static_cast<const G*>(a.L);
+  G* __restrict__ Y = static_cast<G*>(a.Y);
+  const int64_t Il = a.Il, m = a.m, n = a.n;
+  const int64_t F = INNER ? a.Il * a.Ir : a.Ir;
+  const int64_t f0 = bx * BF;
+  const int64_t i0 = by * BN;
+  const int t = threadIdx.x;
+  const int lane = t & 63;
+  const int w = t >> 6;
+
+  // Staging tasks: one row and one group of KV consecutive k.
+  //   X, inner: row = id % BF (consecutive threads walk adjacent fibers),
+  //             kg = id / BF.
+  //   X, lead : kg = id % KG, row = id / KG (threads walk along k).
+  //   L       : kg = id % KG, row = id / KG.
+  // Every element's byte offset from the chunk's uniform base pointer is
+  // fixed for the whole k loop, so it is computed once here (32-bit: the
+  // host splits launches so that each stays below 2^31 bytes). Rows past
+  // the end are clamped to the last row: they only feed accumulator rows
+  // or columns that are never stored. Only the k tail needs zeros.
+  uint32_t xo[XT][KV], lo_[LT][KV];
+  int xkg[XT], lkg[LT];
+  const int64_t xkstep = INNER ? Il : 1;  // elements per unit of k in X
+#pragma unroll
+  for (int s = 0; s < XT; ++s) {
+    const int id = t + s * kThreads;
+    int64_t rowoff;
+    int kg;
+    if (INNER) {
+      kg = (id / BF) % KG;
+      int64_t r = f0 + id % BF;
+      r = r < F ? r : F - 1;
+      rowoff = fiber_offset(r, Il, m);
+    } else {
+      kg = id % KG;
+      int64_t f = f0 + (id / KG) % BF;
+      f = f < F ? f : F - 1;
+      rowoff = f * m;
+    }
+    xkg[s] = kg;
+#pragma unroll
+    for (int e = 0; e < KV; ++e)
+      xo[s][e] = static_cast<uint32_t>((rowoff + (kg * KV + e) * xkstep) * sizeof(G));
+  }
+#pragma unroll
+  for (int s = 0; s < LT; ++s) {
+    const int id = t + s * kThreads;
+    const int kg = id % KG;
+    int64_t i = i0 + (id / KG) % BN;
+    i = i < n ? i : n - 1;
+    lkg[s] = kg;
+#pragma unroll
+    for (int e = 0; e < KV; ++e)
+      lo_[s][e] = static_cast<uint32_t>((i * a.rs + (kg * KV + e) * a.cs) * sizeof(G));
+  }
+  G xr[XT][KV], lr[LT][KV];
+
+  // CHECK: the chunk reaches past k = m; those k read as zero.
+  auto load_chunk = [&](int64_t k0, auto check) {
+    constexpr bool CHECK = decltype(check)::value;
+    const char* xb = reinterpret_cast<const char*>(X + k0 * xkstep);
+    const char* lb = reinterpret_cast<const char*>(L + k0 * a.cs);
+#pragma unroll
+    for (int s = 0; s < XT; ++s)
+#pragma unroll
+      for (int e = 0; e < KV; ++e) {
+        if constexpr (CHECK) {
+          const bool ok = k0 + xkg[s] * KV + e < m;
+          // a k past m may lie past the tensor: read X[0] instead, then zero
+          const G v = ok ? *reinterpret_cast<const G*>(xb + xo[s][e]) : X[0];
+          xr[s][e] = ok ? v : G(0);
+        } else {
+          xr[s][e] = *reinterpret_cast<const G*>(xb + xo[s][e]);
+        }
+      }
+#pragma unroll
+    for (int s = 0; s < LT; ++s)
+#pragma unroll
+      for (int e = 0; e < KV; ++e) {
+        if constexpr (CHECK) {
+          const bool ok = k0 + lkg[s] * KV + e < m;
+          const G v = ok ? *reinterpret_cast<const G*>(lb + lo_[s][e]) : L[0];
+          lr[s][e] = ok ? v : G(0);
+        } else {
+          lr[s][e] = *reinterpret_cast<const G*>(lb + lo_[s][e]);
+        }
+      }
+  };
+  // Registers -> LDS; the split forms write P bf16 planes.
+  auto store_rows = [&](auto& tile, int row, int kg, const G (&v)[KV]) {
+    if constexpr (SPLIT) {
+      bf16x8_t pl[P];
+#pragma unroll
+      for (int e = 0; e < KV; ++e) {
+        __bf16 o[P];
+        split_bf16<P>(v[e], o);
+#pragma unroll
+        for (int p = 0; p < P; ++p) pl[p][e] = o[p];
+      }
+#pragma unroll
+      for (int p = 0; p < P; ++p) *reinterpret_cast<bf16x8_t*>(&tile[p][row][kg * KV]) = pl[p];
+    } else {
+      FragT f;
+#pragma unroll
+      for (int e = 0; e < KV; ++e) f[e] = v[e];
+      *reinterpret_cast<FragT*>(&tile[0][row][kg * KV]) = f;
+    }
+  };
+  auto store_chunk = [&](int buf) {
+#pragma unroll
+    for (int s = 0; s < XT; ++s) {
+      const int id = t + s * kThreads;
+      const int row = INNER ? id % BF : id / KG;
+      const int kg = INNER ? id / BF : id % KG;
+      if (row < BF && kg < KG) store_rows(sX[buf], row, kg, xr[s]);
+    }
+#pragma unroll
+    for (int s = 0; s < LT; ++s) {
+      const int id = t + s * kThreads;
+      const int row = id / KG;
+      const int kg = id % KG;
+      if (row < BN) store_rows(sL[buf], row, kg, lr[s]);
+    }
+  };
+
+  acc_t hi[QB][PB], lo[QB][PB];
+#pragma unroll
+  for (int q = 0; q < QB; ++q)
+#pragma unroll
+    for (int p = 0; p < PB; ++p) {
+      hi[q][p] = acc_t{};
+      lo[q][p] = acc_t{};
+    }
+
+  const int c = lane & 15;
+  const int g = lane >> 4;
+  const int64_t nchunks = (m + BK - 1) / BK;
+  const int64_t nfull = m / BK;  // chunks with no k past m
+  using Checked = std::true_type;
+  using Unchecked = std::false_type;
+  if (nchunks > 0) {
+    if (nfull > 0)
+      load_chunk(0, Unchecked{});
+    else
+      load_chunk(0, Checked{});
+    store_chunk(0);
+  }
+  __syncthreads();
+  for (int64_t ch = 0; ch < nchunks; ++ch) {
+    const int buf = static_cast<int>(ch & 1);
+    if (ch + 1 < nfull)
+      load_chunk((ch + 1) * BK, Unchecked{});
+    else if (ch + 1 < nchunks)
+      load_chunk((ch + 1) * BK, Checked{});
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += MK) {
+      FragT xa[FB][P];
+#pragma unroll
+      for (int fb = 0; fb < FB; ++fb)
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+          xa[fb][p] = *reinterpret_cast<const FragT*>(
+              &sX[buf][p][w * 16 * FB + fb * 16 + c][kk + KV * g]);
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        FragT la[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+          la[p] = *reinterpret_cast<const FragT*>(&sL[buf][p][nb * 16 + c][kk + KV * g]);
+#pragma unroll
+        for (int fb = 0; fb < FB; ++fb) {
+          // A operand = MFMA rows, B = MFMA (memory-contiguous) columns
+          if constexpr (INNER)
+            macro_step<FORM>(la, xa[fb], hi[nb][fb], lo[nb][fb]);
+          else
+            macro_step<FORM>(xa[fb], la, hi[fb][nb], lo[fb][nb]);
+        }
+      }
+    }
+    if (ch + 1 < nchunks) store_chunk(buf ^ 1);
+    __syncthreads();
+  }
+
+  // Store: MFMA column = lane & 15 is the memory-contiguous output index.
+#pragma unroll
+  for (int q = 0; q < QB; ++q)
+#pragma unroll
+    for (int p = 0; p < PB; ++p) {
+      acc_t val = hi[q][p];
+      if constexpr (SPLIT) val = hi[q][p] + lo[q][p];
+      if (INNER) {
+        const int64_t r = f0 + w * 16 * FB + p * 16 + c;
+        if (r >= F) continue;
+        G* yb = Y + fiber_offset(r, Il, n);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t i = i0 + q * 16 + FT::row(lane, v);
+          if (i < n) {
+            G* dst = yb + Il * i;
+            *dst = a.accumulate ? *dst + val[v] : val[v];
+          }
+        }
+      } else {
+        const int64_t i = i0 + p * 16 + c;
+        if (i >= n) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t f = f0 + w * 16 * FB + q * 16 + FT::row(lane, v);
+          if (f < F) {
+            G* dst = Y + i + n * f;
+            *dst = a.accumulate ? *dst + val[v] : val[v];
+          }
+        }
+      }
+    }
+}
+
+}  // namespace tile
+}  // namespace kp

@@ -252,6 +252,92 @@ def expm(A, tau=1.0):
     return E if batched else E[0]
 
 
+class BatchedTucker:
+    """Many independent Tucker operators (and optionally their gradients):
+    one persistent launch per dependency level (kp_tucker_batched).
+
+    Ts[k] is a tensor of order d_k, Ls[k] its d_k factors (no None); all share
+    a dtype. With ``Gs`` (cotangents, shapes of the outputs) the backward runs
+    in the same launch: ``dT[k]`` (if need_dT) and ``dL[k][mu]`` (if need_dL).
+    Outputs, workspace and the device copy of the plan are allocated once
+    here; ``run()`` only enqueues the level launches on the current stream,
+    so it can be captured into a CUDA/HIP graph and replayed; the inputs can
+    be overwritten in place between runs.
+    """
+
+    def __init__(self, Ts, Ls, prec="native", Gs=None, need_dT=True, need_dL=True):
+        if len(Ts) != len(Ls):
+            raise ValueError("one factor list per tensor")
+        _check_device(*Ts)
+        self.prec = _prec(prec)
+        self.Ts = [_canon(T) for T in Ts]
+        self.Ls = [list(L) for L in Ls]
+        self.Gs = None if Gs is None else [_canon(G) for G in Gs]
+        count = len(Ts)
+        dev = Ts[0].device if count else torch.device("cuda")
+        self.S = []
+        self.dT = [] if Gs is not None and need_dT else None
+        self.dL = [] if Gs is not None and need_dL else None
+        items = (_lib.KpBatchItem * max(count, 1))()
+        self._keep = []
+        for k in range(count):
+            T, L = self.Ts[k], self.Ls[k]
+            d = T.dim()
+            if len(L) != d or any(x is None for x in L):
+                raise ValueError("each problem needs all d factors")
+            S = torch.empty([x.shape[0] for x in L], dtype=T.dtype, device=T.device)
+            self.S.append(S)
+            it = items[k]
+            it.T = _tdesc(T, True)
+            it.S = _tdesc(S, True)
+            for j, x in enumerate(L[::-1]):
+                it.L[j] = _mdesc(x)
+            if self.Gs is not None:
+                G = self.Gs[k]
+                if list(G.shape) != list(S.shape):
+                    raise ValueError("cotangent shape must match the output")
+                it.G = _tdesc(G, True)
+                if self.dT is not None:
+                    dT = torch.empty_like(T)
+                    self.dT.append(dT)
+                    it.dT = _tdesc(dT, True)
+                if self.dL is not None:
+                    dls = [torch.empty(x.shape, dtype=T.dtype, device=T.device) for x in L]
+                    self.dL.append(dls)
+                    for j, x in enumerate(dls[::-1]):
+                        it.dL[j] = _mdesc(x)
+        lb = lib()
+        self._items = items
+        self.count = count
+        ws_bytes = lb.kp_batch_workspace(count, items, self.prec)
+        plan_bytes = lb.kp_batch_plan_bytes(count, items, self.prec)
+        if count and (ws_bytes == 0 or plan_bytes == 0):
+            raise ValueError("invalid batch (see include/kp.h for the limits)")
+        self.ws = torch.empty(max(ws_bytes, 256), dtype=torch.uint8, device=dev)
+        self.plan_host = (ctypes.c_char * max(plan_bytes, 1))()
+        check(lb.kp_batch_plan(count, items, self.prec, self.ws.data_ptr(), self.ws.numel(),
+                               self.plan_host, plan_bytes), "kp_batch_plan")
+        self.plan_bytes = plan_bytes
+        self._upload()
+        nt = ctypes.c_int64()
+        ns = ctypes.c_int()
+        nl = ctypes.c_int()
+        check(lb.kp_batch_info(self.plan_host, ctypes.byref(nt), ctypes.byref(ns),
+                               ctypes.byref(nl)), "kp_batch_info")
+        self.ntasks, self.nstages, self.nlevels = nt.value, ns.value, nl.value
+
+    def _upload(self):
+        host = torch.frombuffer(bytearray(bytes(self.plan_host)), dtype=torch.uint8)
+        self.plan_dev = host.to(self.ws.device)
+        torch.cuda.current_stream().synchronize()
+
+    def run(self):
+        st = lib().kp_tucker_batched(self.plan_dev.data_ptr(), self.plan_host,
+                                     self.ws.data_ptr(), self.ws.numel(), _stream())
+        check(st, "kp_tucker_batched")
+        return self.S
+
+
 def force_tile(nb=0, fb=0, bk=0, occ=0):
     """Force the mode-kernel tile for later launches (nb=0 resets)."""
     check(lib().kp_force_tile(nb, fb, bk, occ), "kp_force_tile")
