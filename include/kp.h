@@ -211,11 +211,12 @@ int kp_expm_f64(const double* A, int64_t n, int64_t count, double tau, double* E
  * Force the tile of every subsequent mode-product launch in this process:
  * nb 16-wide blocks along n per workgroup, fb 16-wide fiber blocks per wave,
  * bk the k-chunk staged in LDS (32 for the BF16 forms), occ the waves per
- * SIMD the variant's register budget targets (0: any). nb <= 0 restores the
+ * SIMD the variant's register budget targets (0: any), pf the prefetch
+ * distance in k-chunks (1 or 2; 0: 1). nb <= 0 restores the
  * default choice. A launch whose forced tile is not a compiled variant fails
  * with KP_ERR_HIP (hipErrorInvalidValue). Not thread-safe; meant for tests and
  * the tile-timing driver. */
-int kp_force_tile(int nb, int fb, int bk, int occ);
+int kp_force_tile(int nb, int fb, int bk, int occ, int pf);
 
 /* ---- utilities ------------------------------------------------------------- */
 const char* kp_strerror(int status);

@@ -75,7 +75,7 @@ SIGNATURES = {
     "kp_batch_plan": (ctypes.c_int, [ctypes.c_int, P(KpBatchItem), ctypes.c_int, _V, _S, _V, _S]),
     "kp_batch_info": (ctypes.c_int, [_V, P(ctypes.c_int64), P(ctypes.c_int), P(ctypes.c_int)]),
     "kp_tucker_batched": (ctypes.c_int, [_V, _V, _V, _S, _V]),
-    "kp_force_tile": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "kp_force_tile": (ctypes.c_int, [ctypes.c_int] * 5),
     "kp_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "kp_version": (ctypes.c_int, []),
     "kp_last_hip_error": (ctypes.c_int, []),

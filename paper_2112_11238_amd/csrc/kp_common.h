@@ -32,9 +32,9 @@ struct ModeArgs {
 // Tile choice for the mode kernels. nb = 16-wide blocks along n per
 // workgroup, fb = 16-wide fiber blocks per wave (4 waves per workgroup),
 // bk = k-chunk staged in LDS per step, occ = waves per SIMD the variant's
-// register budget targets (0: any).
+// register budget targets (0: any), pf = prefetch distance in chunks (0: 1).
 struct ModeTile {
-  int nb, fb, bk, occ;
+  int nb, fb, bk, occ, pf;
 };
 
 // Launch one mu-mode product; returns a hipError_t.

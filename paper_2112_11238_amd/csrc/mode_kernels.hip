@@ -29,25 +29,46 @@ namespace {
 
 using namespace tile;
 
-template <int FORM, int NB, int FB, int BK, int OCC, bool INNER>
-__global__ __launch_bounds__(kThreads, OCC) void mode_kernel(ModeArgs a) {
+// Workgroups are dealt to the XCDs round-robin (workgroup id mod kXcds), each
+// XCD with its own L2. The launch is one-dimensional and the id is remapped
+// so that each XCD receives a contiguous range of logical tiles, ordered
+// with the n tiles of one fiber tile adjacent: those read the same input
+// fibers, which then come from that XCD's L2 instead of HBM.
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ void xcd_tile(int64_t gx, int64_t gy, int64_t* bx, int64_t* by) {
+  const int64_t total = gx * gy;
+  const int64_t id = blockIdx.x;
+  const int64_t xcd = id % kXcds, local = id / kXcds;
+  const int64_t per = total / kXcds, rem = total % kXcds;
+  const int64_t logical = xcd * per + (xcd < rem ? xcd : rem) + local;
+  *by = logical % gy;
+  *bx = logical / gy;
+}
+
+template <int FORM, int NB, int FB, int BK, int OCC, int PF, bool INNER>
+__global__ __launch_bounds__(kThreads, OCC) void mode_kernel(ModeArgs a, int64_t gx,
+                                                             int64_t gy) {
   __shared__ __attribute__((aligned(16))) char lds[mode_lds_bytes<FORM, NB, FB, BK>()];
-  mode_tile<FORM, NB, FB, BK, INNER>(a, blockIdx.x, blockIdx.y, lds);
+  int64_t bx, by;
+  xcd_tile(gx, gy, &bx, &by);
+  mode_tile<FORM, NB, FB, BK, INNER, PF>(a, bx, by, lds);
 }
 
 // ---------------------------------------------------------------------------
 // Dispatch over the compiled tile variants.
 // ---------------------------------------------------------------------------
-using KernelFn = void (*)(ModeArgs);
+using KernelFn = void (*)(ModeArgs, int64_t, int64_t);
 
 struct Variant {
-  int form, nb, fb, bk, occ;
+  int form, nb, fb, bk, occ, pf;
   KernelFn lead, inner;
 };
 
-#define KP_V(FORM, NB, FB, BK, OCC)                                   \
-  {FORM, NB, FB, BK, OCC, mode_kernel<FORM, NB, FB, BK, OCC, false>, \
-   mode_kernel<FORM, NB, FB, BK, OCC, true>}
+#define KP_VP(FORM, NB, FB, BK, OCC, PF)                                      \
+  {FORM, NB, FB, BK, OCC, PF, mode_kernel<FORM, NB, FB, BK, OCC, PF, false>, \
+   mode_kernel<FORM, NB, FB, BK, OCC, PF, true>}
+#define KP_V(FORM, NB, FB, BK, OCC) KP_VP(FORM, NB, FB, BK, OCC, 1)
 
 const Variant kVariants[] = {
     // FP64
@@ -72,12 +93,19 @@ const Variant kVariants[] = {
     KP_V(FORM_BF16X6, 4, 2, 32, 2), KP_V(FORM_BF16X6, 4, 1, 32, 2), KP_V(FORM_BF16X6, 8, 1, 32, 2),
     KP_V(FORM_BF16X6, 8, 2, 32, 1), KP_V(FORM_BF16X6, 13, 1, 32, 1), KP_V(FORM_BF16X6, 16, 1, 32, 1),
     KP_V(FORM_BF16X6, 13, 1, 32, 2), KP_V(FORM_BF16X6, 7, 1, 32, 2),
+    // prefetch distance 2
+    KP_VP(FORM_F64, 7, 1, 16, 2, 2), KP_VP(FORM_F64, 4, 1, 16, 2, 2),
+    KP_VP(FORM_F64, 8, 1, 16, 2, 2), KP_VP(FORM_F64, 7, 1, 8, 2, 2),
+    KP_VP(FORM_F32, 8, 1, 16, 2, 2), KP_VP(FORM_F32, 4, 1, 16, 2, 2),
+    KP_VP(FORM_F32, 7, 1, 16, 2, 2), KP_VP(FORM_F32, 13, 1, 16, 2, 2),
+    KP_VP(FORM_BF16X3, 4, 1, 32, 2, 2), KP_VP(FORM_BF16X3, 8, 1, 32, 2, 2),
+    KP_VP(FORM_BF16X6, 4, 1, 32, 2, 2), KP_VP(FORM_BF16X6, 8, 1, 32, 2, 2),
 };
 
 const Variant* find_variant(int form, const ModeTile& t) {
   for (const Variant& v : kVariants)
     if (v.form == form && v.nb == t.nb && v.fb == t.fb && v.bk == t.bk &&
-        (t.occ == 0 || v.occ == t.occ))
+        (t.occ == 0 || v.occ == t.occ) && (t.pf == 0 ? v.pf == 1 : v.pf == t.pf))
       return &v;
   return nullptr;
 }
@@ -88,6 +116,7 @@ const Variant* find_variant(int form, const ModeTile& t) {
 ModeTile pick_tile(int form, int64_t n) {
   ModeTile t{};
   t.occ = 0;
+  t.pf = 0;
   if (form == FORM_F64) {
     t.bk = 16;
     if (n <= 16) { t.nb = 1; t.fb = 4; }
@@ -147,10 +176,10 @@ hipError_t launch_mode(int form, const ModeArgs& a, const ModeTile* force,
     const int64_t F = inner ? p.Il * p.Ir : p.Ir;
     const int64_t gx = (F + bf - 1) / bf;
     const int64_t gy = (p.n + bn - 1) / bn;
-    if (gx > 0x7fffffffLL || gy > 65535) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL(inner ? v->inner : v->lead,
-                       dim3(static_cast<unsigned>(gx), static_cast<unsigned>(gy)),
-                       dim3(kThreads), 0, stream, p);
+    // one-dimensional grid: its size in work-items must fit 32 bits
+    if (gx * gy > 0xffffffffLL / kThreads) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(inner ? v->inner : v->lead, dim3(static_cast<unsigned>(gx * gy)),
+                       dim3(kThreads), 0, stream, p, gx, gy);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -131,7 +131,10 @@ constexpr size_t mode_lds_bytes() {
 // One output tile (fiber block bx, n block by) of a mu-mode product,
 // computed by the 256 threads of a workgroup; `lds` holds
 // mode_lds_bytes<...>() bytes, 16-byte aligned.
-template <int FORM, int NB, int FB, int BK, bool INNER>
+// PF: prefetch distance in k-chunks (1 or 2). With 2, two register sets
+// alternate so the global loads of chunk c+2 are in flight while chunk c
+// computes (LDS stays double buffered).
+template <int FORM, int NB, int FB, int BK, bool INNER, int PF = 1>
 __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t bx, int64_t by,
                                           char* __restrict__ lds) {
   using FT = FormT<FORM>;
@@ -213,11 +216,14 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t bx, int64_t
     for (int e = 0; e < KV; ++e)
       lo_[s][e] = static_cast<uint32_t>((i * a.rs + (kg * KV + e) * a.cs) * sizeof(G));
   }
-  G xr[XT][KV], lr[LT][KV];
+  static_assert(PF == 1 || PF == 2, "prefetch distance 1 or 2");
+  G xr[PF][XT][KV], lr[PF][LT][KV];
 
   // CHECK: the chunk reaches past k = m; those k read as zero.
-  auto load_chunk = [&](int64_t k0, auto check) {
+  // SET: the register set the chunk is loaded into.
+  auto load_chunk = [&](int64_t k0, auto check, auto set) {
     constexpr bool CHECK = decltype(check)::value;
+    constexpr int SET = decltype(set)::value;
     const char* xb = reinterpret_cast<const char*>(X + k0 * xkstep);
     const char* lb = reinterpret_cast<const char*>(L + k0 * a.cs);
 #pragma unroll
@@ -228,9 +234,9 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t bx, int64_t
           const bool ok = k0 + xkg[s] * KV + e < m;
           // a k past m may lie past the tensor: read X[0] instead, then zero
           const G v = ok ? *reinterpret_cast<const G*>(xb + xo[s][e]) : X[0];
-          xr[s][e] = ok ? v : G(0);
+          xr[SET][s][e] = ok ? v : G(0);
         } else {
-          xr[s][e] = *reinterpret_cast<const G*>(xb + xo[s][e]);
+          xr[SET][s][e] = *reinterpret_cast<const G*>(xb + xo[s][e]);
         }
       }
 #pragma unroll
@@ -240,9 +246,9 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t bx, int64_t
         if constexpr (CHECK) {
           const bool ok = k0 + lkg[s] * KV + e < m;
           const G v = ok ? *reinterpret_cast<const G*>(lb + lo_[s][e]) : L[0];
-          lr[s][e] = ok ? v : G(0);
+          lr[SET][s][e] = ok ? v : G(0);
         } else {
-          lr[s][e] = *reinterpret_cast<const G*>(lb + lo_[s][e]);
+          lr[SET][s][e] = *reinterpret_cast<const G*>(lb + lo_[s][e]);
         }
       }
   };
@@ -266,20 +272,21 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t bx, int64_t
       *reinterpret_cast<FragT*>(&tile[0][row][kg * KV]) = f;
     }
   };
-  auto store_chunk = [&](int buf) {
+  auto store_chunk = [&](int buf, auto set) {
+    constexpr int SET = decltype(set)::value;
 #pragma unroll
     for (int s = 0; s < XT; ++s) {
       const int id = t + s * kThreads;
       const int row = INNER ? id % BF : id / KG;
       const int kg = INNER ? id / BF : id % KG;
-      if (row < BF && kg < KG) store_rows(sX[buf], row, kg, xr[s]);
+      if (row < BF && kg < KG) store_rows(sX[buf], row, kg, xr[SET][s]);
     }
 #pragma unroll
     for (int s = 0; s < LT; ++s) {
       const int id = t + s * kThreads;
       const int row = id / KG;
       const int kg = id % KG;
-      if (row < BN) store_rows(sL[buf], row, kg, lr[s]);
+      if (row < BN) store_rows(sL[buf], row, kg, lr[SET][s]);
     }
   };
 
@@ -298,20 +305,16 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t bx, int64_t
   const int64_t nfull = m / BK;  // chunks with no k past m
   using Checked = std::true_type;
   using Unchecked = std::false_type;
-  if (nchunks > 0) {
-    if (nfull > 0)
-      load_chunk(0, Unchecked{});
+  using Set0 = std::integral_constant<int, 0>;
+  using Set1 = std::integral_constant<int, PF - 1>;
+  // load chunk `ch` (k0 = ch*BK) into register set SET, checked only at the tail
+  auto load = [&](int64_t ch, auto set) {
+    if (ch < nfull)
+      load_chunk(ch * BK, Unchecked{}, set);
     else
-      load_chunk(0, Checked{});
-    store_chunk(0);
-  }
-  __syncthreads();
-  for (int64_t ch = 0; ch < nchunks; ++ch) {
-    const int buf = static_cast<int>(ch & 1);
-    if (ch + 1 < nfull)
-      load_chunk((ch + 1) * BK, Unchecked{});
-    else if (ch + 1 < nchunks)
-      load_chunk((ch + 1) * BK, Checked{});
+      load_chunk(ch * BK, Checked{}, set);
+  };
+  auto compute = [&](int buf) {
 #pragma unroll
     for (int kk = 0; kk < BK; kk += MK) {
       FragT xa[FB][P];
@@ -337,8 +340,40 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t bx, int64_t
         }
       }
     }
-    if (ch + 1 < nchunks) store_chunk(buf ^ 1);
+  };
+  if constexpr (PF == 1) {
+    if (nchunks > 0) {
+      load(0, Set0{});
+      store_chunk(0, Set0{});
+    }
     __syncthreads();
+    for (int64_t ch = 0; ch < nchunks; ++ch) {
+      const int buf = static_cast<int>(ch & 1);
+      if (ch + 1 < nchunks) load(ch + 1, Set0{});
+      compute(buf);
+      if (ch + 1 < nchunks) store_chunk(buf ^ 1, Set0{});
+      __syncthreads();
+    }
+  } else {
+    // set 0 carries even chunks, set 1 odd ones; chunk c is loaded two
+    // chunks before it is computed and stored to LDS one chunk before
+    if (nchunks > 0) {
+      load(0, Set0{});
+      if (nchunks > 1) load(1, Set1{});
+      store_chunk(0, Set0{});
+    }
+    __syncthreads();
+    for (int64_t ch = 0; ch < nchunks; ch += 2) {
+      if (ch + 2 < nchunks) load(ch + 2, Set0{});
+      compute(0);
+      if (ch + 1 < nchunks) store_chunk(1, Set1{});
+      __syncthreads();
+      if (ch + 1 >= nchunks) break;
+      if (ch + 3 < nchunks) load(ch + 3, Set1{});
+      compute(1);
+      if (ch + 2 < nchunks) store_chunk(0, Set0{});
+      __syncthreads();
+    }
   }
 
   // Store: MFMA column = lane & 15 is the memory-contiguous output index.

@@ -338,6 +338,6 @@ class BatchedTucker:
         return self.S
 
 
-def force_tile(nb=0, fb=0, bk=0, occ=0):
+def force_tile(nb=0, fb=0, bk=0, occ=0, pf=0):
     """Force the mode-kernel tile for later launches (nb=0 resets)."""
-    check(lib().kp_force_tile(nb, fb, bk, occ), "kp_force_tile")
+    check(lib().kp_force_tile(nb, fb, bk, occ, pf), "kp_force_tile")

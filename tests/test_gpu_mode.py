@@ -119,6 +119,11 @@ TILES = {
                (8, 1, 32, 2), (8, 2, 32, 1), (13, 1, 32, 1), (16, 1, 32, 1), (13, 1, 32, 2),
                (7, 1, 32, 2)],
 }
+# prefetch-distance-2 variants (nb, fb, bk, occ, pf)
+TILES["native64"] += [(7, 1, 16, 2, 2), (4, 1, 16, 2, 2), (8, 1, 16, 2, 2), (7, 1, 8, 2, 2)]
+TILES["native32"] += [(8, 1, 16, 2, 2), (4, 1, 16, 2, 2), (7, 1, 16, 2, 2), (13, 1, 16, 2, 2)]
+TILES["bf16x3"] += [(4, 1, 32, 2, 2), (8, 1, 32, 2, 2)]
+TILES["bf16x6"] += [(4, 1, 32, 2, 2), (8, 1, 32, 2, 2)]
 
 
 @pytest.mark.parametrize("dt,prec", FORMS)
