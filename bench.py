@@ -41,7 +41,9 @@ PEAK = {  # MI355X published dense peaks, TFLOP/s
 }
 HBM_PEAK_GBS = 8000.0
 FORMS = [("f64", "native"), ("f32", "native"), ("f32", "bf16x3"), ("f32", "bf16x6")]
-MODE_KERNEL_SRC = os.path.join(ROOT, "paper_2112_11238_amd", "csrc", "mode_kernels.hip")
+CSRC = os.path.join(ROOT, "paper_2112_11238_amd", "csrc")
+MODE_KERNEL_SRC = [os.path.join(CSRC, f) for f in ("mode_kernels.hip", "mode_tile.h",
+                                                    "kp_common.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_mode_f64_cube200.json")
 
 
@@ -53,6 +55,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="all", help="comma list of f64,f32,bf16x3,bf16x6")
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="only launch the FP64 mode products of cube200 (--steps each) and a "
+                         "plain 512 MiB device copy, for hardware-counter runs")
     return ap.parse_args()
 
 
@@ -65,9 +70,12 @@ def form_name(dt, prec):
     return dt if prec == "native" else prec
 
 
-def source_hash(path):
-    with open(path, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+def source_hash(paths):
+    h = hashlib.sha256()
+    for path in paths:
+        with open(path, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def load_traffic(per_launch_units):
@@ -104,12 +112,44 @@ def cpu_baseline(T, Ls, flops, budget_s=12.0):
                       f"repetitions in {el:.1f} s, numpy float64"}
 
 
+def traffic_probe(args):
+    """Launches for a counter run: each FP64 mu-mode product of cube200 with
+    the default tiles, then a plain device-to-device copy of known size whose
+    counter readings calibrate the HBM byte counters."""
+    import torch
+
+    import paper_2112_11238_amd as kp
+    dev = torch.device("cuda:0")
+    T, Ls = kp_workloads.cube200(seed=0)
+    Td = torch.tensor(T, dtype=torch.float64, device=dev)
+    Lds = [torch.tensor(L, dtype=torch.float64, device=dev) for L in Ls]
+    out = torch.empty_like(Td)
+    for mu in (1, 2, 3):
+        for _ in range(args.steps):
+            kp.mump(Td, Lds[mu - 1], mu, out=out)
+    torch.cuda.synchronize()
+    copy_bytes = 512 << 20
+    a = torch.ones(copy_bytes // 8, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"probe": "traffic", "mode_launches_per_mu": args.steps,
+                      "mode_bytes_in_out": 2 * Td.numel() * 8,
+                      "copy_bytes_read": copy_bytes, "copy_bytes_written": copy_bytes,
+                      "copy_launches": 3, "kernel_source_sha256_16": source_hash(MODE_KERNEL_SRC)}),
+          flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU; multi-GPU runs are "
-                                   "not part of this build (see DESIGN.md, sharding)"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only: there is no "
+                                   "multi-GPU path, only one GPU's share is measured"}))
         sys.exit(2)
+    if args.traffic_probe:
+        traffic_probe(args)
+        return
     import torch
 
     import oracle
