@@ -218,6 +218,57 @@ int kp_expm_f64(const double* A, int64_t n, int64_t count, double tau, double* E
  * the tile-timing driver. */
 int kp_force_tile(int nb, int fb, int bk, int occ, int pf);
 
+/* Tile table. Before its built-in defaults, the library looks the tile of
+ * each mu-mode product up in a process-wide table keyed by the product's
+ * form and exact 3-index view; kp_tucker, kp_tucker_backward, kp_mump and
+ * the batched planner (when its executor compiles that tile) all consult it,
+ * a tile forced by kp_force_tile takes precedence. The table is filled by a
+ * tuning driver that times the compiled variants on the products of a
+ * problem (the Python package's `tune` module) or from a saved table.
+ * Thread-safe.
+ *   form   0 FP64, 1 FP32, 3 BF16x3, 6 BF16x6 (the last two on FP32 data)
+ *   Il, m, n, Ir   the view: X is (Il, m, Ir), Y = (Il, n, Ir), L is n x m
+ *   nb, fb, bk, occ, pf   the tile, as for kp_force_tile (occ, pf as compiled) */
+typedef struct {
+  int32_t form, pad0_;
+  int64_t Il, m, n, Ir;
+  int32_t nb, fb, bk, occ, pf, pad1_;
+} kp_tune_entry; /* 64 bytes */
+
+/* Insert or replace the entry for e's key. KP_ERR_NULL if e is NULL;
+ * KP_ERR_VALUE if the key is invalid (form not 0/1/3/6, a size < 1) or no
+ * compiled variant has that tile (occ 0 or pf 0 take the first compiled
+ * match, which is what is stored). */
+int kp_tune_set(const kp_tune_entry* e);
+/* The tile a product with this key gets when no tile is forced: returns 1
+ * and fills *out from the table if the key is tuned, 0 and fills *out with
+ * the built-in default otherwise; KP_ERR_NULL / KP_ERR_VALUE on bad input. */
+int kp_tune_lookup(int form, int64_t Il, int64_t m, int64_t n, int64_t Ir, kp_tune_entry* out);
+/* Number of entries; kp_tune_list copies the first min(cap, count) entries
+ * (in key order) to out (may be NULL when cap is 0) and returns the count. */
+int kp_tune_count(void);
+int kp_tune_list(kp_tune_entry* out, int cap);
+/* Remove every entry. */
+int kp_tune_clear(void);
+/* The mu-mode products a call launches for these shapes, in launch order,
+ * each as a table key with the tile it gets now (table or default):
+ *   which 0  kp_tucker without a cache (planned minimum-flop order)
+ *         1  kp_tucker with a cache, and the forward partials that
+ *            kp_tucker_backward recomputes (definition order)
+ *         2  kp_tucker_backward's cotangent sweep Q_{mu-1} = Q_mu x_mu L_mu^T
+ *            (mu = d..1; when dT is not wanted the sweep stops early)
+ * Writes min(cap, count) entries (out may be NULL if cap is 0) and returns
+ * the count; argument errors as kp_tucker_workspace's validation
+ * (KP_ERR_NULL for which = 2 with an identity factor, KP_ERR_VALUE for a
+ * bad `which`). Data pointers are not read. */
+int kp_tucker_products(const kp_tensor* T, const kp_matrix* const L[], int prec, int which,
+                       kp_tune_entry* out, int cap);
+/* The compiled tiles for a form: batch = 0 the standalone mode kernels
+ * (5 ints per tile: nb, fb, bk, occ, pf), batch = 1 the batched executor
+ * (nb, fb, bk, 0, 0). Writes min(cap, count) tiles to out (NULL if cap is
+ * 0) and returns the count; KP_ERR_VALUE for an unknown form. */
+int kp_tile_variants(int form, int batch, int32_t* out, int cap);
+
 /* ---- utilities ------------------------------------------------------------- */
 const char* kp_strerror(int status);
 int kp_version(void);

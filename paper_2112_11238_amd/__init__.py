@@ -7,6 +7,7 @@ thin torch binding (ops) that only marshals arguments.
 """
 from .ops import (mump, tucker, tucker_with_cache, tucker_backward,  # noqa: F401
                   tucker_autograd, TuckerFunction, expm, BatchedTucker, force_tile)
+from . import tune  # noqa: F401,E402
 
 __all__ = ["mump", "tucker", "tucker_with_cache", "tucker_backward", "tucker_autograd",
-           "TuckerFunction", "expm", "BatchedTucker", "force_tile"]
+           "TuckerFunction", "expm", "BatchedTucker", "force_tile", "tune"]

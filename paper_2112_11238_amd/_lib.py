@@ -43,6 +43,14 @@ class KpBatchItem(ctypes.Structure):
                 ("G", KpTensor), ("dT", KpTensor), ("dL", KpMatrix * KP_MAX_ORDER)]
 
 
+class KpTuneEntry(ctypes.Structure):
+    _fields_ = [("form", ctypes.c_int32), ("pad0_", ctypes.c_int32),
+                ("Il", ctypes.c_int64), ("m", ctypes.c_int64), ("n", ctypes.c_int64),
+                ("Ir", ctypes.c_int64),
+                ("nb", ctypes.c_int32), ("fb", ctypes.c_int32), ("bk", ctypes.c_int32),
+                ("occ", ctypes.c_int32), ("pf", ctypes.c_int32), ("pad1_", ctypes.c_int32)]
+
+
 class KpError(RuntimeError):
     def __init__(self, status, where):
         self.status = status
@@ -76,6 +84,16 @@ SIGNATURES = {
     "kp_batch_info": (ctypes.c_int, [_V, P(ctypes.c_int64), P(ctypes.c_int), P(ctypes.c_int)]),
     "kp_tucker_batched": (ctypes.c_int, [_V, _V, _V, _S, _V]),
     "kp_force_tile": (ctypes.c_int, [ctypes.c_int] * 5),
+    "kp_tune_set": (ctypes.c_int, [P(KpTuneEntry)]),
+    "kp_tune_lookup": (ctypes.c_int, [ctypes.c_int, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                                      ctypes.c_int64, P(KpTuneEntry)]),
+    "kp_tune_count": (ctypes.c_int, []),
+    "kp_tune_list": (ctypes.c_int, [P(KpTuneEntry), ctypes.c_int]),
+    "kp_tune_clear": (ctypes.c_int, []),
+    "kp_tucker_products": (ctypes.c_int, [_T, _MA, ctypes.c_int, ctypes.c_int, P(KpTuneEntry),
+                                          ctypes.c_int]),
+    "kp_tile_variants": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, P(ctypes.c_int32),
+                                        ctypes.c_int]),
     "kp_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "kp_version": (ctypes.c_int, []),
     "kp_last_hip_error": (ctypes.c_int, []),

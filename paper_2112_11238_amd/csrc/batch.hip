@@ -505,6 +505,21 @@ int batch_blocks() {
 }
 
 }  // namespace
+
+int list_batch_variants(int form, int32_t* out, int cap) {
+  int nv;
+  const BVar* vs = host_vars(form, &nv);
+  for (int i = 0; i < nv && i < cap; ++i) {
+    int32_t* o = out + 5 * i;
+    o[0] = vs[i].nb;
+    o[1] = vs[i].fb;
+    o[2] = vs[i].bk;
+    o[3] = 0;
+    o[4] = 0;
+  }
+  return nv;
+}
+
 }  // namespace kp
 
 using namespace kp;

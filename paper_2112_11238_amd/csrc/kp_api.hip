@@ -504,4 +504,60 @@ int kp_tucker_backward(const kp_tensor* G, const kp_tensor* T, const kp_matrix* 
   return KP_OK;
 }
 
+int kp_tucker_products(const kp_tensor* T, const kp_matrix* const* L, int prec, int which,
+                       kp_tune_entry* out, int cap) {
+  int st = validate_tucker_args(T, L, prec);
+  if (st) return st;
+  if (which < 0 || which > 2) return KP_ERR_VALUE;
+  if (cap > 0 && !out) return KP_ERR_NULL;
+  const int d = T->d;
+  if (which == 2)
+    for (int k = 0; k < d; ++k)
+      if (!L[k]) return KP_ERR_NULL;
+  const int form = form_of(prec, T->dtype);
+  int count = 0;
+  auto emit = [&](const ModeArgs& a) {
+    if (count < cap) {
+      const ModeTile t = default_mode_tile(form, a);
+      ModeTile r;
+      if (!resolve_mode_tile(form, t, &r)) r = t;
+      kp_tune_entry& e = out[count];
+      e.form = form;
+      e.pad0_ = 0;
+      e.Il = a.Il;
+      e.m = a.m;
+      e.n = a.n;
+      e.Ir = a.Ir;
+      e.nb = r.nb;
+      e.fb = r.fb;
+      e.bk = r.bk;
+      e.occ = r.occ;
+      e.pf = r.pf;
+      e.pad1_ = 0;
+    }
+    ++count;
+  };
+  if (which < 2) {
+    ChainPlan p;
+    make_chain(*T, L, which == 1, &p);
+    for (int s = 0; s < p.count; ++s) {
+      const int k = p.order[s];
+      emit(mode_args(nullptr, nullptr, p.dims[s], d, k, *L[k], 0));
+    }
+  } else {
+    int64_t qdims[KP_MAX_ORDER];
+    for (int k = 0; k < d; ++k) qdims[k] = L[k]->rows;
+    for (int k = d - 1; k >= 0; --k) {
+      kp_matrix Lt = *L[k];
+      Lt.rows = L[k]->cols;
+      Lt.cols = L[k]->rows;
+      Lt.rs = L[k]->cs;
+      Lt.cs = L[k]->rs;
+      emit(mode_args(nullptr, nullptr, qdims, d, k, Lt, 0));
+      qdims[k] = L[k]->cols;
+    }
+  }
+  return count;
+}
+
 }  // extern "C"

@@ -44,5 +44,15 @@ hipError_t launch_mode(int form, const ModeArgs& a, const ModeTile* force,
 ModeTile default_mode_tile(int form, const ModeArgs& a);
 // Whether a tile is one of the compiled variants for this form/layout.
 bool mode_tile_supported(int form, const ModeArgs& a, const ModeTile& t);
+// The compiled variant matching t (occ 0 / pf 0: first match), written to
+// *out with its occ and pf filled in; false if none.
+bool resolve_mode_tile(int form, const ModeTile& t, ModeTile* out);
+// Built-in default tile by form and output size.
+ModeTile builtin_mode_tile(int form, int64_t n);
+// Tile-table lookup (kp_tune.hip); false if the key has no entry.
+bool tuned_tile(int form, int64_t Il, int64_t m, int64_t n, int64_t Ir, ModeTile* out);
+// Compiled tiles as (nb, fb, bk, occ, pf) quintuples; returns the count.
+int list_mode_variants(int form, int32_t* out, int cap);
+int list_batch_variants(int form, int32_t* out, int cap);
 
 }  // namespace kp

@@ -88,11 +88,13 @@ const Variant kVariants[] = {
     KP_V(FORM_BF16X3, 4, 2, 32, 2), KP_V(FORM_BF16X3, 4, 1, 32, 2), KP_V(FORM_BF16X3, 8, 1, 32, 2),
     KP_V(FORM_BF16X3, 8, 2, 32, 1), KP_V(FORM_BF16X3, 13, 1, 32, 1), KP_V(FORM_BF16X3, 16, 1, 32, 1),
     KP_V(FORM_BF16X3, 13, 1, 32, 2), KP_V(FORM_BF16X3, 7, 1, 32, 2), KP_V(FORM_BF16X3, 4, 2, 64, 2),
+    KP_V(FORM_BF16X3, 1, 2, 32, 2), KP_V(FORM_BF16X3, 2, 1, 32, 2),
     // BF16 x6
     KP_V(FORM_BF16X6, 1, 4, 32, 2), KP_V(FORM_BF16X6, 2, 4, 32, 2), KP_V(FORM_BF16X6, 2, 2, 32, 2),
     KP_V(FORM_BF16X6, 4, 2, 32, 2), KP_V(FORM_BF16X6, 4, 1, 32, 2), KP_V(FORM_BF16X6, 8, 1, 32, 2),
     KP_V(FORM_BF16X6, 8, 2, 32, 1), KP_V(FORM_BF16X6, 13, 1, 32, 1), KP_V(FORM_BF16X6, 16, 1, 32, 1),
     KP_V(FORM_BF16X6, 13, 1, 32, 2), KP_V(FORM_BF16X6, 7, 1, 32, 2),
+    KP_V(FORM_BF16X6, 1, 2, 32, 2), KP_V(FORM_BF16X6, 2, 1, 32, 2),
     // prefetch distance 2
     KP_VP(FORM_F64, 7, 1, 16, 2, 2), KP_VP(FORM_F64, 4, 1, 16, 2, 2),
     KP_VP(FORM_F64, 8, 1, 16, 2, 2), KP_VP(FORM_F64, 7, 1, 8, 2, 2),
@@ -142,11 +144,41 @@ ModeTile pick_tile(int form, int64_t n) {
 
 }  // namespace
 
-ModeTile default_mode_tile(int form, const ModeArgs& a) { return pick_tile(form, a.n); }
+ModeTile builtin_mode_tile(int form, int64_t n) { return pick_tile(form, n); }
+
+ModeTile default_mode_tile(int form, const ModeArgs& a) {
+  ModeTile t;
+  if (tuned_tile(form, a.Il, a.m, a.n, a.Ir, &t)) return t;
+  return pick_tile(form, a.n);
+}
 
 bool mode_tile_supported(int form, const ModeArgs& a, const ModeTile& t) {
   (void)a;
   return find_variant(form, t) != nullptr;
+}
+
+bool resolve_mode_tile(int form, const ModeTile& t, ModeTile* out) {
+  const Variant* v = find_variant(form, t);
+  if (!v) return false;
+  *out = ModeTile{v->nb, v->fb, v->bk, v->occ, v->pf};
+  return true;
+}
+
+int list_mode_variants(int form, int32_t* out, int cap) {
+  int count = 0;
+  for (const Variant& v : kVariants) {
+    if (v.form != form) continue;
+    if (count < cap) {
+      int32_t* o = out + 5 * count;
+      o[0] = v.nb;
+      o[1] = v.fb;
+      o[2] = v.bk;
+      o[3] = v.occ;
+      o[4] = v.pf;
+    }
+    ++count;
+  }
+  return count;
 }
 
 hipError_t launch_mode(int form, const ModeArgs& a, const ModeTile* force,

@@ -16,5 +16,10 @@ int main(void) {
          KP_ERR_SHAPE, KP_ERR_DTYPE, KP_ERR_ALIAS, KP_ERR_WORKSPACE, KP_ERR_HIP, KP_ERR_VALUE);
   printf("prec %d %d %d dtype %d %d maxorder %d\n", KP_PREC_NATIVE, KP_PREC_BF16X3,
          KP_PREC_BF16X6, KP_F64, KP_F32, KP_MAX_ORDER);
+  printf("kp_tune_entry %zu form %zu Il %zu m %zu n %zu Ir %zu nb %zu fb %zu bk %zu occ %zu pf %zu\n",
+         sizeof(kp_tune_entry), offsetof(kp_tune_entry, form), offsetof(kp_tune_entry, Il),
+         offsetof(kp_tune_entry, m), offsetof(kp_tune_entry, n), offsetof(kp_tune_entry, Ir),
+         offsetof(kp_tune_entry, nb), offsetof(kp_tune_entry, fb), offsetof(kp_tune_entry, bk),
+         offsetof(kp_tune_entry, occ), offsetof(kp_tune_entry, pf));
   return 0;
 }

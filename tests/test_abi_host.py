@@ -67,6 +67,10 @@ def test_struct_layout_matches_header(L):
     assert [int(p[1]), int(p[2]), int(p[3])] == [L.KP_PREC_NATIVE, L.KP_PREC_BF16X3,
                                                  L.KP_PREC_BF16X6]
     assert [int(p[5]), int(p[6]), int(p[8])] == [L.KP_F64, L.KP_F32, L.KP_MAX_ORDER]
+    e = out[4].split()
+    assert e[0] == "kp_tune_entry" and int(e[1]) == ctypes.sizeof(L.KpTuneEntry) == 64
+    for name, off in zip(e[2::2], e[3::2]):
+        assert getattr(L.KpTuneEntry, name).offset == int(off), name
 
 
 def test_strerror_and_version(lib, L):

@@ -1,0 +1,168 @@
+"""Host-side checks of the tile table and the tuning helpers (no kernel is
+launched): validation, lookup, listing, the product views a call reports,
+and that the batched planner takes its tiles from the table."""
+import ctypes
+import itertools
+import json
+
+import numpy as np
+import pytest
+import torch
+
+from test_abi_host import matrix, mlist, no_device, tensor
+from test_batch_plan_host import make_items, plan, Alloc
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2112_11238_amd import _lib
+    return _lib
+
+
+@pytest.fixture(scope="module")
+def lib(L):
+    return L.load()
+
+
+@pytest.fixture()
+def tune(lib):
+    from paper_2112_11238_amd import tune as t
+    t.clear()
+    yield t
+    t.clear()
+
+
+def entry(L, form, Il, m, n, Ir, tile):
+    e = L.KpTuneEntry()
+    e.form, e.Il, e.m, e.n, e.Ir = form, Il, m, n, Ir
+    e.nb, e.fb, e.bk, e.occ, e.pf = tile
+    return e
+
+
+def test_variant_lists(lib, tune):
+    for form in (0, 1, 3, 6):
+        mode = tune.variants(form)
+        assert len(mode) >= 10
+        assert len(set(mode)) == len(mode)
+        bk = 16 if form in (0, 1) else 32
+        assert any(v[2] == bk for v in mode)
+        # every tile of the batched executor has a standalone kernel with the
+        # same (nb, fb, bk): the throughput tuner times it there
+        for v in tune.variants(form, batch=True):
+            assert v[3:] == (0, 0)
+            assert any(w[:3] == v[:3] for w in mode), (form, v)
+    assert lib.kp_tile_variants(2, 0, None, 0) == -9
+    assert lib.kp_tile_variants(0, 2, None, 0) == -9
+    assert lib.kp_tile_variants(0, 0, None, 5) == -1
+
+
+def test_set_lookup_list_clear(lib, L, tune):
+    assert lib.kp_tune_set(None) == -1
+    assert lib.kp_tune_set(ctypes.byref(entry(L, 2, 1, 8, 8, 8, (4, 1, 16, 0, 0)))) == -9
+    assert lib.kp_tune_set(ctypes.byref(entry(L, 0, 0, 8, 8, 8, (4, 1, 16, 0, 0)))) == -9
+    assert lib.kp_tune_set(ctypes.byref(entry(L, 0, 1, 8, 8, 8, (5, 1, 16, 0, 0)))) == -9
+    assert lib.kp_tune_set(ctypes.byref(entry(L, 0, 1, 8, 8, 8, (4, 1, 16, 0, 3)))) == -9
+    assert lib.kp_tune_count() == 0
+    # default first
+    tuned, tile = tune.lookup("f64", 40, 200, 200, 200)
+    assert not tuned and tile[:3] == (7, 1, 16)
+    tune.set_tile("f64", 40, 200, 200, 200, (4, 1, 16))
+    tuned, tile = tune.lookup("f64", 40, 200, 200, 200)
+    assert tuned and tile[:3] == (4, 1, 16) and tile[3] > 0 and tile[4] == 1  # resolved
+    tune.set_tile("f64", 40, 200, 200, 200, (7, 1, 8, 2, 2))     # replace
+    assert tune.lookup("f64", 40, 200, 200, 200) == (True, (7, 1, 8, 2, 2))
+    assert tune.lookup("f32", 40, 200, 200, 200)[0] is False      # the form is in the key
+    assert tune.lookup("f64", 41, 200, 200, 200)[0] is False
+    tune.set_tile("bf16x3", 1, 30, 20, 1000, (2, 2, 32))
+    ents = tune.entries()
+    assert len(ents) == 2 == lib.kp_tune_count()
+    assert [e["form"] for e in ents] == [0, 3]                    # key order
+    assert lib.kp_tune_list(None, 0) == 2
+    tune.clear()
+    assert lib.kp_tune_count() == 0 and tune.entries() == []
+
+
+def test_save_load_round_trip(tune, tmp_path):
+    tune.set_tile("f32", 1, 64, 48, 4096, (4, 1, 16))
+    tune.set_tile("f64", 16, 20, 30, 7, (2, 2, 16))
+    before = tune.entries()
+    path = tmp_path / "table.json"
+    tune.save(str(path))
+    rec = json.loads(path.read_text())
+    assert rec["entries"] == before
+    tune.clear()
+    assert tune.load(str(path)) == 2
+    assert tune.entries() == before
+
+
+def views(m, n, order, backward=False):
+    """The 3-index views of a chain in column-major (canonical) mode order."""
+    d = len(m)
+    cur = list(m)
+    out = []
+    if backward:
+        cur = list(n)
+        for k in reversed(range(d)):
+            Il, Ir = int(np.prod(cur[:k])), int(np.prod(cur[k + 1:]))
+            out.append((Il, n[k], m[k], Ir))
+            cur[k] = m[k]
+        return out
+    for k in order:
+        Il, Ir = int(np.prod(cur[:k])), int(np.prod(cur[k + 1:]))
+        out.append((Il, m[k], n[k], Ir))
+        cur[k] = n[k]
+    return out
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_products_report_the_chain_views(lib, L, tune, seed):
+    rng = np.random.default_rng(70 + seed)
+    d = int(rng.integers(1, 6))
+    tm = [int(x) for x in rng.integers(1, 12, size=d)]   # torch shape
+    tn = [int(x) for x in rng.integers(1, 12, size=d)]
+    T = torch.zeros(tm, dtype=torch.float64)             # pointers are not read
+    Ls = [torch.zeros((tn[k], tm[k]), dtype=torch.float64) for k in range(d)]
+    m, n = tm[::-1], tn[::-1]                              # canonical order
+    got = [(p["Il"], p["m"], p["n"], p["Ir"]) for p in tune.products(T, Ls)]
+    Td = tensor(L, m)
+    arr = mlist(L, [matrix(L, n[k], m[k]) for k in range(d)])
+    order = (ctypes.c_int * 8)()
+    cnt = ctypes.c_int()
+    assert lib.kp_tucker_order(ctypes.byref(Td), arr, order, ctypes.byref(cnt)) == 0
+    planned = [order[k] - 1 for k in range(cnt.value)]
+    assert got == views(m, n, planned)
+    got1 = [(p["Il"], p["m"], p["n"], p["Ir"]) for p in tune.products(T, Ls, which="forward_cached")]
+    assert got1 == views(m, n, list(range(d)))
+    got2 = [(p["Il"], p["m"], p["n"], p["Ir"]) for p in tune.products(T, Ls, which="backward")]
+    assert got2 == views(m, n, None, backward=True)
+    # the reported tile follows the table
+    p0 = tune.products(T, Ls)[0]
+    tune.set_tile("f64", p0["Il"], p0["m"], p0["n"], p0["Ir"], (2, 4, 16))
+    assert tune.products(T, Ls)[0]["nb"] == 2
+    with pytest.raises(Exception):
+        tune.products(T, Ls, which="nope")
+
+
+@no_device
+def test_batch_plan_takes_tiles_from_the_table(lib, L, tune):
+    shapes = [((20, 30, 40), (24, 16, 40)), ((33, 17), (50, 9))]
+    alloc = Alloc()
+    items = make_items(L, shapes, 1, True, alloc)
+    _, st0, _, _ = plan(lib, L, items, len(shapes), 0)
+    bvars = tune.variants("f32", batch=True)
+    modes = [s for s in st0 if s.kind == 0]
+    assert modes
+    # move every mode stage to a tile the executor has, other than its current one
+    for s in modes:
+        a = s.m
+        cur = bvars[s.variant // 2]
+        other = next(v for v in bvars if v != cur)
+        tune.set_tile("f32", a.Il, a.m, a.n, a.Ir, other[:3])
+    _, st1, _, _ = plan(lib, L, items, len(shapes), 0)
+    m1 = [s for s in st1 if s.kind == 0]
+    assert len(m1) == len(modes)
+    for s in m1:
+        a = s.m
+        _, tile = tune.lookup("f32", a.Il, a.m, a.n, a.Ir)
+        assert bvars[s.variant // 2][:3] == tile[:3]
+        assert (s.variant & 1) == (1 if a.Il > 1 else 0)
