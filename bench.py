@@ -55,6 +55,12 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="all", help="comma list of f64,f32,bf16x3,bf16x6")
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--workload", default="cube200",
+                    choices=["cube200", "small2d", "heat128", "interp6d", "batch64"],
+                    help="cube200 is the headline line; the others time the remaining "
+                         "configurations (one JSON line each)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="tune the tiles of every launched product before timing")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="only launch the FP64 mode products of cube200 (--steps each) and a "
                          "plain 512 MiB device copy, for hardware-counter runs")
@@ -149,6 +155,9 @@ def main():
         sys.exit(2)
     if args.traffic_probe:
         traffic_probe(args)
+        return
+    if args.workload != "cube200":
+        print(json.dumps(WORKLOAD_BENCHES[args.workload](args)), flush=True)
         return
     import torch
 
@@ -269,6 +278,294 @@ def main():
         line["cpu_baseline"] = cpu_baseline(T, Ls, flops)
     line["oracle_first_call_s"] = round(oracle_once, 2)
     print(json.dumps(line), flush=True)
+
+
+# ---------------------------------------------------------------------------
+# The other configurations (not the headline line): --workload NAME
+# ---------------------------------------------------------------------------
+
+def _events_ms(fn, steps, warmup):
+    """Average ms per call of fn() over `steps` calls, events on the current
+    stream around the whole run (inputs resident, warm)."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def _graph_ms(fn, steps, warmup):
+    """Average ms per replay of fn() captured into one HIP graph."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            fn()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    return _events_ms(g.replay, steps, warmup), g
+
+
+def _launch_ms(kp, dtype, prec, view, steps):
+    """Average ms of one mu-mode product launch on the view (Il, m, n, Ir),
+    HIP events around every launch on the launch stream."""
+    import torch
+    Il, m, n, Ir = view
+    X = torch.randn((Ir, m, Il), dtype=dtype, device="cuda")
+    L = torch.randn((n, m), dtype=dtype, device="cuda")
+    Y = torch.empty((Ir, n, Il), dtype=dtype, device="cuda")
+    for _ in range(2):
+        kp.mump(X, L, 2, prec=prec, out=Y)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * steps)]
+    for k in range(steps):
+        ev[2 * k].record()
+        kp.mump(X, L, 2, prec=prec, out=Y)
+        ev[2 * k + 1].record()
+    torch.cuda.synchronize()
+    return statistics.mean(ev[2 * k].elapsed_time(ev[2 * k + 1]) for k in range(steps))
+
+
+def _views(kp, Td, Lds, prec, which="forward"):
+    return [(p["Il"], p["m"], p["n"], p["Ir"]) for p in kp.tune.products(Td, Lds, prec, which)]
+
+
+def _line(args, metric, value, unit, ms, dtype, workload, extra, higher=True):
+    line = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": higher,
+            "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic",
+            "config": workload}
+    line.update(extra)
+    return line
+
+
+def _form_list(args, default):
+    if args.forms == "all":
+        return default
+    want = set(args.forms.split(","))
+    return [f for f in default if form_name(*f) in want]
+
+
+def _rel(got, ref):
+    return float(np.abs(got - ref).max() / np.abs(ref).max())
+
+
+def bench_small2d(args):
+    """d = 2, 50 x 50 FP64 (and the other forms): latency of one Tucker call,
+    eager and replayed from a HIP graph; each mode alone."""
+    import torch
+
+    import oracle
+    import paper_2112_11238_amd as kp
+    T, Ls = kp_workloads.small2d(seed=0)
+    flops = kp_workloads.tucker_flops(T.shape, [L.shape[0] for L in Ls])
+    ref = oracle.tucker(T, Ls)
+    forms = {}
+    for dt, prec in _form_list(args, FORMS):
+        tdt = torch.float64 if dt == "f64" else torch.float32
+        Td = torch.tensor(T, dtype=tdt, device="cuda")
+        Lds = [torch.tensor(L, dtype=tdt, device="cuda") for L in Ls]
+        if args.autotune:
+            kp.tune.autotune(Td, Lds, prec=prec, reps=20)
+        S = kp.tucker(Td, Lds, prec=prec)
+        torch.cuda.synchronize()
+        eager = _events_ms(lambda: kp.tucker(Td, Lds, prec=prec), args.steps * 10, args.warmup)
+        graph, _ = _graph_ms(lambda: kp.tucker(Td, Lds, prec=prec), args.steps * 10, args.warmup)
+        modes = [_launch_ms(kp, tdt, prec, v, args.steps) for v in _views(kp, Td, Lds, prec)]
+        forms[form_name(dt, prec)] = {
+            "us_per_call_eager": round(eager * 1e3, 2), "us_per_call_graph": round(graph * 1e3, 2),
+            "us_per_mode_launch": [round(x * 1e3, 2) for x in modes],
+            "rel_err_maxnorm": _rel(S.double().cpu().numpy(), ref)}
+    head = forms.get("f64") or next(iter(forms.values()))
+    t0 = time.perf_counter()
+    reps = 0
+    while time.perf_counter() - t0 < 3.0:
+        oracle.tucker(T, Ls)
+        reps += 1
+    cpu_us = (time.perf_counter() - t0) / reps * 1e6
+    return _line(args, "Tucker-op latency small2d (d=2, 50x50), us per call, graph replay",
+                 head["us_per_call_graph"], "us", head["us_per_call_graph"] / 1e3, "f64",
+                 {"workload": "small2d: Tucker operator d=2, m=n=50, standard-normal T and "
+                              "factors, seed 0; value is the FP64 form replayed from a graph",
+                  "flops_per_call": flops},
+                 {"forms": forms, "cpu_baseline": {"value": round(cpu_us, 2), "unit": "us",
+                                                   "cores": _threads(), "kind": "oracle",
+                                                   "sample": f"{reps} oracle calls"}},
+                 higher=False)
+
+
+def _threads():
+    try:
+        from threadpoolctl import threadpool_info
+        return int(max([p.get("num_threads", 1) for p in threadpool_info()] or [1]))
+    except Exception:  # pragma: no cover
+        return os.cpu_count()
+
+
+def bench_heat128(args):
+    """d = 3, n = 128: E_mu = exp(tau A_mu) built in FP64 on the device, then
+    S = V x_1 E_1 x_2 E_2 x_3 E_3 in every form."""
+    import torch
+
+    import oracle
+    import paper_2112_11238_amd as kp
+    V, As, tau = kp_workloads.heat128(seed=0)
+    n = V.shape[0]
+    h = 1.0 / (n + 1)
+    A = torch.tensor(np.stack(As), dtype=torch.float64, device="cuda")
+    expm_ms = _events_ms(lambda: kp.expm(A, tau), args.steps, args.warmup)
+    E = kp.expm(A, tau)
+    torch.cuda.synchronize()
+    Eref = oracle.expm_fd_laplacian_dirichlet(n, h, tau)
+    expm_err = max(_rel(E[k].cpu().numpy(), Eref) for k in range(3))
+    Es = [E[k].contiguous() for k in range(3)]
+    ref = oracle.tucker(V, [Eref] * 3)
+    flops = kp_workloads.tucker_flops(V.shape, [n] * 3)
+    forms = {}
+    for dt, prec in _form_list(args, FORMS):
+        tdt = torch.float64 if dt == "f64" else torch.float32
+        Vd = torch.tensor(V, dtype=tdt, device="cuda")
+        Ed = [x.to(tdt) for x in Es]
+        if args.autotune:
+            kp.tune.autotune(Vd, Ed, prec=prec, reps=10)
+        S = kp.tucker(Vd, Ed, prec=prec)
+        torch.cuda.synchronize()
+        ms = _events_ms(lambda: kp.tucker(Vd, Ed, prec=prec), args.steps, args.warmup)
+        modes = [_launch_ms(kp, tdt, prec, v, args.steps) for v in _views(kp, Vd, Ed, prec)]
+        forms[form_name(dt, prec)] = {
+            "tflops": round(flops / (ms * 1e-3) / 1e12, 3), "ms_per_step": round(ms, 5),
+            "mode_ms": [round(x, 5) for x in modes],
+            "rel_err_maxnorm": _rel(S.double().cpu().numpy(), ref)}
+    head = forms.get("f64") or next(iter(forms.values()))
+    return _line(args, "Tucker-op TFLOP/s heat128 (d=3, n=128, exp(tau A) factors)",
+                 head["tflops"], "TFLOP/s", head["ms_per_step"], "f64",
+                 {"workload": "heat128: V ~ N(0,1) 128^3 seed 0, A = tridiag(1,-2,1)/h^2, "
+                              "h = 1/129, tau = 1e-3, E = exp(tau A) built in FP64 on the "
+                              "device; value is the FP64 form", "flops_per_step": flops},
+                 {"forms": forms, "expm": {"ms_three_factors": round(expm_ms, 4),
+                                           "rel_err_vs_dst_closed_form": expm_err}})
+
+
+def bench_interp6d(args):
+    """d = 6, 16^6 -> 24^6 Lagrange interpolation in FP32 (and the BF16
+    splits): forward, and forward + backward (dT and every dL)."""
+    import torch
+
+    import paper_2112_11238_amd as kp
+    T, Ls = kp_workloads.interp6d(seed=0)
+    m, n = list(T.shape), [L.shape[0] for L in Ls]
+    fwd_flops = kp_workloads.tucker_flops(m, n)
+    # backward: the cotangent sweep (mode d down to 1, L^T) and one gram per mode
+    bwd_flops = kp_workloads.tucker_flops(n[::-1], m[::-1])
+    for mu in range(6):
+        bwd_flops += 2 * n[mu] * m[mu] * int(np.prod(n[:mu])) * int(np.prod(m[mu + 1:]))
+    forms = {}
+    roof = None
+    for dt, prec in _form_list(args, FORMS[1:]):
+        Td = torch.tensor(T, dtype=torch.float32, device="cuda")
+        Lds = [torch.tensor(L, dtype=torch.float32, device="cuda") for L in Ls]
+        G = torch.randn(n, dtype=torch.float32, device="cuda")
+        if args.autotune:
+            kp.tune.autotune(Td, Lds, prec=prec, backward=True, reps=5)
+        fwd = _events_ms(lambda: kp.tucker(Td, Lds, prec=prec), args.steps, args.warmup)
+
+        def step():
+            S, cache = kp.tucker_with_cache(Td, Lds, prec=prec)
+            kp.tucker_backward(G, Td, Lds, prec, cache=cache)
+        both = _events_ms(step, args.steps, args.warmup)
+        views = _views(kp, Td, Lds, prec)
+        launch = [_launch_ms(kp, torch.float32, prec, v, args.steps) for v in views]
+        min_bytes = (int(np.prod(m)) + int(np.prod(n))) * 4
+        unfused = sum((Il * mm * Ir + Il * nn * Ir) * 4 for Il, mm, nn, Ir in views)
+        forms[form_name(dt, prec)] = {
+            "fwd_ms": round(fwd, 4), "fwd_tflops": round(fwd_flops / (fwd * 1e-3) / 1e12, 3),
+            "fwd_min_bytes_gbs": round(min_bytes / (fwd * 1e-3) / 1e9, 1),
+            "fwd_unfused_bytes_gbs": round(unfused / (fwd * 1e-3) / 1e9, 1),
+            "fwd_bwd_ms": round(both, 4),
+            "fwd_bwd_tflops": round((fwd_flops + bwd_flops) / (both * 1e-3) / 1e12, 3),
+            "launch_ms": [round(x, 4) for x in launch]}
+        if roof is None:
+            k = int(np.argmax(launch))
+            Il, mm, nn, Ir = views[k]
+            byts = (Il * mm * Ir + Il * nn * Ir) * 4 + nn * mm * 4
+            gbs = byts / (launch[k] * 1e-3) / 1e9
+            roof = {"kernel": f"mode_kernel<{form_name(dt, prec)}> largest forward launch "
+                              f"(Il={Il}, m={mm}, n={nn}, Ir={Ir})",
+                    "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                    "avg_launch_ms": round(launch[k], 4), "bytes_per_launch": byts,
+                    "traffic": None}
+    head = forms.get("f32") or next(iter(forms.values()))
+    return _line(args, "Tucker-op TFLOP/s interp6d (d=6, 16^6 -> 24^6, FP32), forward + backward",
+                 head["fwd_bwd_tflops"], "TFLOP/s", head["fwd_bwd_ms"], "f32",
+                 {"workload": "interp6d: T ~ N(0,1) 16^6 seed 0, six 24x16 Lagrange factors "
+                              "(Chebyshev nodes to 24 equispaced points); value is FP32 "
+                              "forward + backward (forward with cache, dT and all dL)",
+                  "fwd_flops": fwd_flops, "bwd_flops": bwd_flops},
+                 {"forms": forms, "roofline": roof})
+
+
+def bench_batch64(args):
+    """64 independent d = 4 problems (sizes in [16, 64]), forward + backward
+    in one batched executor run, replayed from a HIP graph."""
+    import torch
+
+    import paper_2112_11238_amd as kp
+    sizes, items = kp_workloads.batch64(seed=0)
+    fwd = bwd = 0
+    for k in range(len(items)):
+        m = [int(x) for x in sizes[k]]
+        fwd += kp_workloads.tucker_flops(m, m)
+        bwd += kp_workloads.tucker_flops(m[::-1], m[::-1])
+        for mu in range(4):
+            bwd += 2 * m[mu] * m[mu] * int(np.prod(m)) // m[mu]
+    forms = {}
+    for prec in ("native", "bf16x3", "bf16x6"):
+        name = form_name("f32", prec)
+        if args.forms != "all" and name not in args.forms.split(","):
+            continue
+        Td = [torch.tensor(T, dtype=torch.float32, device="cuda") for T, _ in items]
+        Ld = [[torch.tensor(L, dtype=torch.float32, device="cuda") for L in Ls] for _, Ls in items]
+        Gd = [torch.randn(T.shape, dtype=torch.float32, device="cuda") for T in Td]
+        rec = {}
+        for tuned in ([False, True] if args.autotune else [False]):
+            if tuned:
+                kp.tune.autotune_batch(Td, Ld, prec=prec, backward=True, reps=3)
+            bt_f = kp.BatchedTucker(Td, Ld, prec=prec)
+            bt_b = kp.BatchedTucker(Td, Ld, prec=prec, Gs=Gd)
+            f_ms, _ = _graph_ms(bt_f.run, args.steps, args.warmup)
+            b_ms, _ = _graph_ms(bt_b.run, args.steps, args.warmup)
+            rec["tuned" if tuned else "default"] = {
+                "fwd_ms": round(f_ms, 4), "fwd_tflops": round(fwd / (f_ms * 1e-3) / 1e12, 3),
+                "fwd_bwd_ms": round(b_ms, 4),
+                "fwd_bwd_tflops": round((fwd + bwd) / (b_ms * 1e-3) / 1e12, 3),
+                "levels": bt_b.nlevels, "tasks": int(bt_b.ntasks)}
+            kp.tune.clear()
+        forms[name] = rec
+    head = forms.get("f32") or next(iter(forms.values()))
+    best = max(head.values(), key=lambda r: r["fwd_bwd_tflops"])
+    return _line(args, "Batched Tucker-op TFLOP/s batch64 (64 x d=4, sizes 16..64, FP32), "
+                       "forward + backward, graph replay",
+                 best["fwd_bwd_tflops"], "TFLOP/s", best["fwd_bwd_ms"], "f32",
+                 {"workload": "batch64: 64 tensors of order 4, sizes from seed 0 in [16, 64], "
+                              "L ~ N(0,1)/sqrt(n); forward + backward (dT and all dL) in one "
+                              "batched executor run replayed from a HIP graph",
+                  "fwd_flops": fwd, "bwd_flops": bwd},
+                 {"forms": forms})
+
+
+WORKLOAD_BENCHES = {"small2d": bench_small2d, "heat128": bench_heat128,
+                    "interp6d": bench_interp6d, "batch64": bench_batch64}
 
 
 if __name__ == "__main__":

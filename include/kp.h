@@ -208,15 +208,22 @@ int kp_expm_f64(const double* A, int64_t n, int64_t count, double tau, double* E
                 size_t ws_bytes, hipStream_t stream);
 
 /* ---- tuning ----------------------------------------------------------------
- * Force the tile of every subsequent mode-product launch in this process:
- * nb 16-wide blocks along n per workgroup, fb 16-wide fiber blocks per wave,
- * bk the k-chunk staged in LDS (32 for the BF16 forms), occ the waves per
- * SIMD the variant's register budget targets (0: any), pf the prefetch
- * distance in k-chunks (1 or 2; 0: 1). nb <= 0 restores the
- * default choice. A launch whose forced tile is not a compiled variant fails
- * with KP_ERR_HIP (hipErrorInvalidValue). Not thread-safe; meant for tests and
- * the tile-timing driver. */
-int kp_force_tile(int nb, int fb, int bk, int occ, int pf);
+ * A tile is (nb, fb, bk, occ, pf, kind):
+ *   kind 0  k-loop tile: nb 16-wide blocks along n per workgroup, fb 16-wide
+ *           fiber blocks per wave (4 waves), bk the k-chunk staged in LDS
+ *           per step (32 for the BF16 forms), occ the waves per SIMD the
+ *           variant's register budget targets (0: any), pf the prefetch
+ *           distance in k-chunks (1 or 2; 0: 1);
+ *   kind 1  strip tile for short contractions (m <= bk): the workgroup keeps
+ *           its nb blocks of L rows in LDS and streams many fiber tiles of
+ *           64*fb fibers; bk is the padded contraction length, occ = pf = 0.
+ * kp_force_tile forces the tile of every later mode-product launch in this
+ * process; nb <= 0 restores the table / default choice. KP_ERR_VALUE for a
+ * negative or out-of-range field. A launch whose forced tile is not a
+ * compiled variant (or a strip shorter than m) fails with KP_ERR_HIP
+ * (hipErrorInvalidValue). Not thread-safe; meant for tests and the
+ * tile-timing driver. */
+int kp_force_tile(int nb, int fb, int bk, int occ, int pf, int kind);
 
 /* Tile table. Before its built-in defaults, the library looks the tile of
  * each mu-mode product up in a process-wide table keyed by the product's
@@ -228,17 +235,18 @@ int kp_force_tile(int nb, int fb, int bk, int occ, int pf);
  * Thread-safe.
  *   form   0 FP64, 1 FP32, 3 BF16x3, 6 BF16x6 (the last two on FP32 data)
  *   Il, m, n, Ir   the view: X is (Il, m, Ir), Y = (Il, n, Ir), L is n x m
- *   nb, fb, bk, occ, pf   the tile, as for kp_force_tile (occ, pf as compiled) */
+ *   nb, fb, bk, occ, pf, kind   the tile, as for kp_force_tile (occ, pf as
+ *                               compiled) */
 typedef struct {
   int32_t form, pad0_;
   int64_t Il, m, n, Ir;
-  int32_t nb, fb, bk, occ, pf, pad1_;
+  int32_t nb, fb, bk, occ, pf, kind;
 } kp_tune_entry; /* 64 bytes */
 
 /* Insert or replace the entry for e's key. KP_ERR_NULL if e is NULL;
- * KP_ERR_VALUE if the key is invalid (form not 0/1/3/6, a size < 1) or no
+ * KP_ERR_VALUE if the key is invalid (form not 0/1/3/6, a size < 1), no
  * compiled variant has that tile (occ 0 or pf 0 take the first compiled
- * match, which is what is stored). */
+ * match, which is what is stored), or a strip tile is shorter than m. */
 int kp_tune_set(const kp_tune_entry* e);
 /* The tile a product with this key gets when no tile is forced: returns 1
  * and fills *out from the table if the key is tuned, 0 and fills *out with
@@ -263,10 +271,10 @@ int kp_tune_clear(void);
  * bad `which`). Data pointers are not read. */
 int kp_tucker_products(const kp_tensor* T, const kp_matrix* const L[], int prec, int which,
                        kp_tune_entry* out, int cap);
-/* The compiled tiles for a form: batch = 0 the standalone mode kernels
- * (5 ints per tile: nb, fb, bk, occ, pf), batch = 1 the batched executor
- * (nb, fb, bk, 0, 0). Writes min(cap, count) tiles to out (NULL if cap is
- * 0) and returns the count; KP_ERR_VALUE for an unknown form. */
+/* The compiled tiles for a form: batch = 0 the standalone kernels, batch =
+ * 1 the batched executor; 6 ints per tile (nb, fb, bk, occ, pf, kind).
+ * Writes min(cap, count) tiles to out (NULL if cap is 0) and returns the
+ * count; KP_ERR_VALUE for an unknown form. */
 int kp_tile_variants(int form, int batch, int32_t* out, int cap);
 
 /* ---- utilities ------------------------------------------------------------- */

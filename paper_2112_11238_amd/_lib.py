@@ -48,7 +48,7 @@ class KpTuneEntry(ctypes.Structure):
                 ("Il", ctypes.c_int64), ("m", ctypes.c_int64), ("n", ctypes.c_int64),
                 ("Ir", ctypes.c_int64),
                 ("nb", ctypes.c_int32), ("fb", ctypes.c_int32), ("bk", ctypes.c_int32),
-                ("occ", ctypes.c_int32), ("pf", ctypes.c_int32), ("pad1_", ctypes.c_int32)]
+                ("occ", ctypes.c_int32), ("pf", ctypes.c_int32), ("kind", ctypes.c_int32)]
 
 
 class KpError(RuntimeError):
@@ -83,7 +83,7 @@ SIGNATURES = {
     "kp_batch_plan": (ctypes.c_int, [ctypes.c_int, P(KpBatchItem), ctypes.c_int, _V, _S, _V, _S]),
     "kp_batch_info": (ctypes.c_int, [_V, P(ctypes.c_int64), P(ctypes.c_int), P(ctypes.c_int)]),
     "kp_tucker_batched": (ctypes.c_int, [_V, _V, _V, _S, _V]),
-    "kp_force_tile": (ctypes.c_int, [ctypes.c_int] * 5),
+    "kp_force_tile": (ctypes.c_int, [ctypes.c_int] * 6),
     "kp_tune_set": (ctypes.c_int, [P(KpTuneEntry)]),
     "kp_tune_lookup": (ctypes.c_int, [ctypes.c_int, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
                                       ctypes.c_int64, P(KpTuneEntry)]),

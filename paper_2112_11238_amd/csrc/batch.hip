@@ -211,7 +211,7 @@ int pick_batch_variant(int form, const ModeArgs& a) {
   int best = 0;
   int64_t best_cost = -1;
   for (int i = 0; i < nv; ++i) {
-    if (vs[i].nb == want.nb && vs[i].fb == want.fb && vs[i].bk == want.bk) {
+    if (want.kind == 0 && vs[i].nb == want.nb && vs[i].fb == want.fb && vs[i].bk == want.bk) {
       best = i;
       best_cost = 0;
       break;
@@ -510,12 +510,13 @@ int list_batch_variants(int form, int32_t* out, int cap) {
   int nv;
   const BVar* vs = host_vars(form, &nv);
   for (int i = 0; i < nv && i < cap; ++i) {
-    int32_t* o = out + 5 * i;
+    int32_t* o = out + 6 * i;
     o[0] = vs[i].nb;
     o[1] = vs[i].fb;
     o[2] = vs[i].bk;
     o[3] = 0;
     o[4] = 0;
+    o[5] = 0;
   }
   return nv;
 }

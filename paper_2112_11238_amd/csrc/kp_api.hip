@@ -533,7 +533,7 @@ int kp_tucker_products(const kp_tensor* T, const kp_matrix* const* L, int prec, 
       e.bk = r.bk;
       e.occ = r.occ;
       e.pf = r.pf;
-      e.pad1_ = 0;
+      e.kind = r.kind;
     }
     ++count;
   };

@@ -33,8 +33,10 @@ struct ModeArgs {
 // workgroup, fb = 16-wide fiber blocks per wave (4 waves per workgroup),
 // bk = k-chunk staged in LDS per step, occ = waves per SIMD the variant's
 // register budget targets (0: any), pf = prefetch distance in chunks (0: 1).
+// kind 0: k-loop tile (mode_tile.h); kind 1: strip tile (strip_tile.h) for
+// m <= bk, where bk is the padded contraction length and occ, pf are 0.
 struct ModeTile {
-  int nb, fb, bk, occ, pf;
+  int nb, fb, bk, occ, pf, kind;
 };
 
 // Launch one mu-mode product; returns a hipError_t.
@@ -47,12 +49,19 @@ bool mode_tile_supported(int form, const ModeArgs& a, const ModeTile& t);
 // The compiled variant matching t (occ 0 / pf 0: first match), written to
 // *out with its occ and pf filled in; false if none.
 bool resolve_mode_tile(int form, const ModeTile& t, ModeTile* out);
-// Built-in default tile by form and output size.
-ModeTile builtin_mode_tile(int form, int64_t n);
+// Built-in default tile by form and the mode's sizes.
+ModeTile builtin_mode_tile(int form, int64_t m, int64_t n);
 // Tile-table lookup (kp_tune.hip); false if the key has no entry.
 bool tuned_tile(int form, int64_t Il, int64_t m, int64_t n, int64_t Ir, ModeTile* out);
-// Compiled tiles as (nb, fb, bk, occ, pf) quintuples; returns the count.
+// Compiled tiles as (nb, fb, bk, occ, pf, kind) sextuples; returns the count.
 int list_mode_variants(int form, int32_t* out, int cap);
 int list_batch_variants(int form, int32_t* out, int cap);
+// Strip tiles (strip_kernels.hip): default choice for m <= the form's
+// largest strip (false otherwise), resolution against the compiled list,
+// listing, and the launch of one piece (< 2^31 bytes) of a product.
+bool strip_default(int form, int64_t m, int64_t n, ModeTile* out);
+bool strip_resolve(int form, const ModeTile& t, ModeTile* out);
+int list_strip_variants(int form, int32_t* out, int cap);
+hipError_t launch_strip(int form, const ModeArgs& a, const ModeTile& t, hipStream_t stream);
 
 }  // namespace kp

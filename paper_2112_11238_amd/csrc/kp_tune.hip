@@ -40,7 +40,7 @@ void fill(kp_tune_entry* e, const Key& k, const ModeTile& t) {
   e->bk = t.bk;
   e->occ = t.occ;
   e->pf = t.pf;
-  e->pad1_ = 0;
+  e->kind = t.kind;
 }
 }  // namespace
 
@@ -58,12 +58,14 @@ bool tuned_tile(int form, int64_t Il, int64_t m, int64_t n, int64_t Ir, ModeTile
 
 }  // namespace kp
 
-extern "C" int kp_force_tile(int nb, int fb, int bk, int occ, int pf) {
+extern "C" int kp_force_tile(int nb, int fb, int bk, int occ, int pf, int kind) {
   if (nb <= 0) {
     kp::g_force = false;
     return KP_OK;
   }
-  if (fb <= 0 || bk <= 0 || occ < 0 || pf < 0 || pf > 2) return KP_ERR_VALUE;
+  if (fb <= 0 || bk <= 0 || occ < 0 || pf < 0 || pf > 2 || kind < 0 || kind > 1)
+    return KP_ERR_VALUE;
+  kp::g_forced.kind = kind;
   kp::g_forced.nb = nb;
   kp::g_forced.fb = fb;
   kp::g_forced.bk = bk;
@@ -76,11 +78,13 @@ extern "C" int kp_force_tile(int nb, int fb, int bk, int occ, int pf) {
 extern "C" int kp_tune_set(const kp_tune_entry* e) {
   if (!e) return KP_ERR_NULL;
   if (!kp::valid_key(e->form, e->Il, e->m, e->n, e->Ir)) return KP_ERR_VALUE;
-  if (e->nb <= 0 || e->fb <= 0 || e->bk <= 0 || e->occ < 0 || e->pf < 0 || e->pf > 2)
+  if (e->nb <= 0 || e->fb <= 0 || e->bk <= 0 || e->occ < 0 || e->pf < 0 || e->pf > 2 ||
+      e->kind < 0 || e->kind > 1)
     return KP_ERR_VALUE;
-  kp::ModeTile t{e->nb, e->fb, e->bk, e->occ, e->pf};
+  kp::ModeTile t{e->nb, e->fb, e->bk, e->occ, e->pf, e->kind};
   kp::ModeTile r;
   if (!kp::resolve_mode_tile(e->form, t, &r)) return KP_ERR_VALUE;
+  if (r.kind == 1 && e->m > r.bk) return KP_ERR_VALUE;
   std::lock_guard<std::mutex> lock(kp::g_mu);
   kp::table()[kp::Key{e->form, e->Il, e->m, e->n, e->Ir}] = r;
   return KP_OK;
@@ -92,7 +96,7 @@ extern "C" int kp_tune_lookup(int form, int64_t Il, int64_t m, int64_t n, int64_
   if (!kp::valid_key(form, Il, m, n, Ir)) return KP_ERR_VALUE;
   kp::ModeTile t;
   const bool tuned = kp::tuned_tile(form, Il, m, n, Ir, &t);
-  if (!tuned) t = kp::builtin_mode_tile(form, n);
+  if (!tuned) t = kp::builtin_mode_tile(form, m, n);
   kp::ModeTile r;
   if (!kp::resolve_mode_tile(form, t, &r)) r = t;
   kp::fill(out, kp::Key{form, Il, m, n, Ir}, r);
@@ -124,6 +128,7 @@ extern "C" int kp_tune_clear(void) {
 }
 
 extern "C" int kp_tile_variants(int form, int batch, int32_t* out, int cap) {
+  // six ints per tile: nb, fb, bk, occ, pf, kind
   if (!kp::valid_form(form) || (batch != 0 && batch != 1)) return KP_ERR_VALUE;
   if (cap > 0 && !out) return KP_ERR_NULL;
   if (cap < 0) cap = 0;

@@ -105,6 +105,7 @@ const Variant kVariants[] = {
 };
 
 const Variant* find_variant(int form, const ModeTile& t) {
+  if (t.kind != 0) return nullptr;
   for (const Variant& v : kVariants)
     if (v.form == form && v.nb == t.nb && v.fb == t.fb && v.bk == t.bk &&
         (t.occ == 0 || v.occ == t.occ) && (t.pf == 0 ? v.pf == 1 : v.pf == t.pf))
@@ -115,8 +116,9 @@ const Variant* find_variant(int form, const ModeTile& t) {
 // Default tiles, chosen from tile sweeps on cube200 (m = n = 200) and small
 // modes: FP64 favours 7 blocks along n at 3 waves per SIMD, FP32 8 blocks,
 // the BF16 split forms 4 blocks (n tiles re-read their fibers from L2).
-ModeTile pick_tile(int form, int64_t n) {
+ModeTile pick_tile(int form, int64_t m, int64_t n) {
   ModeTile t{};
+  if (strip_default(form, m, n, &t)) return t;
   t.occ = 0;
   t.pf = 0;
   if (form == FORM_F64) {
@@ -144,24 +146,26 @@ ModeTile pick_tile(int form, int64_t n) {
 
 }  // namespace
 
-ModeTile builtin_mode_tile(int form, int64_t n) { return pick_tile(form, n); }
+ModeTile builtin_mode_tile(int form, int64_t m, int64_t n) { return pick_tile(form, m, n); }
 
 ModeTile default_mode_tile(int form, const ModeArgs& a) {
   ModeTile t;
   if (tuned_tile(form, a.Il, a.m, a.n, a.Ir, &t)) return t;
-  return pick_tile(form, a.n);
-}
-
-bool mode_tile_supported(int form, const ModeArgs& a, const ModeTile& t) {
-  (void)a;
-  return find_variant(form, t) != nullptr;
+  return pick_tile(form, a.m, a.n);
 }
 
 bool resolve_mode_tile(int form, const ModeTile& t, ModeTile* out) {
+  if (t.kind == 1) return strip_resolve(form, t, out);
   const Variant* v = find_variant(form, t);
   if (!v) return false;
-  *out = ModeTile{v->nb, v->fb, v->bk, v->occ, v->pf};
+  *out = ModeTile{v->nb, v->fb, v->bk, v->occ, v->pf, 0};
   return true;
+}
+
+bool mode_tile_supported(int form, const ModeArgs& a, const ModeTile& t) {
+  ModeTile r;
+  if (!resolve_mode_tile(form, t, &r)) return false;
+  return r.kind == 0 || a.m <= r.bk;
 }
 
 int list_mode_variants(int form, int32_t* out, int cap) {
@@ -169,23 +173,29 @@ int list_mode_variants(int form, int32_t* out, int cap) {
   for (const Variant& v : kVariants) {
     if (v.form != form) continue;
     if (count < cap) {
-      int32_t* o = out + 5 * count;
+      int32_t* o = out + 6 * count;
       o[0] = v.nb;
       o[1] = v.fb;
       o[2] = v.bk;
       o[3] = v.occ;
       o[4] = v.pf;
+      o[5] = 0;
     }
     ++count;
   }
-  return count;
+  const int ns = list_strip_variants(form, count < cap ? out + 6 * count : nullptr,
+                                     count < cap ? cap - count : 0);
+  return count + ns;
 }
 
 hipError_t launch_mode(int form, const ModeArgs& a, const ModeTile* force,
                        hipStream_t stream) {
   const ModeTile t = force ? *force : default_mode_tile(form, a);
-  const Variant* v = find_variant(form, t);
-  if (!v) return hipErrorInvalidValue;
+  const bool strip = t.kind == 1;
+  const Variant* v = strip ? nullptr : find_variant(form, t);
+  ModeTile st{};
+  if (strip && (!strip_resolve(form, t, &st) || a.m > st.bk)) return hipErrorInvalidValue;
+  if (!strip && !v) return hipErrorInvalidValue;
   const bool inner = a.Il > 1;
   if (a.Il * a.Ir == 0 || a.n == 0) return hipSuccess;
   // The kernels address each launch's tensors with 32-bit byte offsets:
@@ -205,6 +215,11 @@ hipError_t launch_mode(int form, const ModeArgs& a, const ModeTile* force,
     p.Ir = (a.Ir - b0 < per) ? a.Ir - b0 : per;
     p.X = static_cast<const char*>(a.X) + b0 * a.Il * a.m * es;
     p.Y = static_cast<char*>(a.Y) + b0 * a.Il * a.n * es;
+    if (strip) {
+      const hipError_t e = launch_strip(form, p, st, stream);
+      if (e != hipSuccess) return e;
+      continue;
+    }
     const int64_t F = inner ? p.Il * p.Ir : p.Ir;
     const int64_t gx = (F + bf - 1) / bf;
     const int64_t gy = (p.n + bn - 1) / bn;

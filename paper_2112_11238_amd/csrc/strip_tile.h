@@ -1,0 +1,263 @@
+// Strip tile of the mu-mode product for short contractions (m <= KP <= 64),
+// the HBM-bound regime (Sec. 2, Definition of the mu-mode product; the
+// small-factor products of the interpolation and batched workloads).
+//
+// The whole contraction fits one LDS chunk, so instead of a k loop a
+// workgroup keeps its block of BN rows of L (all m columns) in LDS for its
+// whole life and streams a sequence of fiber tiles through double-buffered
+// LDS: the global loads of the next tile are in flight while the current
+// tile computes and its outputs are stored. One barrier per tile.
+#pragma once
+
+#include "mode_tile.h"
+
+namespace kp {
+namespace tile {
+
+template <int FORM, int NB, int FB, int KP>
+constexpr size_t strip_lds_bytes() {
+  using FT = FormT<FORM>;
+  constexpr int LDK = KP + 16 / sizeof(typename FT::S);
+  return FT::P * (16 * NB + 2 * 64 * FB) * LDK * sizeof(typename FT::S);
+}
+
+// Fiber tiles bx = t0, t0 + tstep, ... < ntiles of n block `by`.
+// VEC (lead layout only): every fiber row starts 16-byte aligned and m is a
+// multiple of KV, so each staging task is one 16-byte load.
+template <int FORM, int NB, int FB, int KP, bool INNER, bool VEC>
+__device__ __forceinline__ void strip_run(const ModeArgs& a, int64_t by, int64_t t0,
+                                          int64_t tstep, int64_t ntiles,
+                                          char* __restrict__ lds) {
+  using FT = FormT<FORM>;
+  using G = typename FT::G;
+  using SE = typename FT::S;
+  using acc_t = typename FT::acc_t;
+  using FragT = Frag<FORM>;
+  constexpr int P = FT::P, KV = FT::KV, MK = FT::MK;
+  constexpr bool SPLIT = FORM == FORM_BF16X3 || FORM == FORM_BF16X6;
+  constexpr int BN = 16 * NB;
+  constexpr int BF = 64 * FB;
+  constexpr int KG = KP / KV;
+  constexpr int LDK = KP + 16 / sizeof(SE);
+  constexpr int XT = (BF * KG + kThreads - 1) / kThreads;
+  constexpr int LT = (BN * KG + kThreads - 1) / kThreads;
+  constexpr int QB = INNER ? NB : FB;
+  constexpr int PB = INNER ? FB : NB;
+  static_assert(KP % MK == 0, "KP must be a multiple of the macro step");
+  static_assert(!INNER || kThreads % BF == 0, "BF must divide the block size");
+  static_assert(!(INNER && VEC), "vector loads are for the lead layout");
+  typedef G GV __attribute__((ext_vector_type(KV)));
+
+  typedef SE LTile[P][BN][LDK];
+  typedef SE XTile[P][BF][LDK];
+  LTile& sL = *reinterpret_cast<LTile*>(lds);
+  XTile* sX = reinterpret_cast<XTile*>(lds + sizeof(LTile));
+
+  const G* __restrict__ X = static_cast<const G*>(a.X);
+  const G* __restrict__ L = static_cast<const G*>(a.L);
+  G* __restrict__ Y = static_cast<G*>(a.Y);
+  // 32-bit index math: the host keeps every launch below 2^31 bytes
+  const uint32_t Il = static_cast<uint32_t>(a.Il), m = static_cast<uint32_t>(a.m);
+  const uint32_t n = static_cast<uint32_t>(a.n);
+  const uint32_t F = static_cast<uint32_t>(INNER ? a.Il * a.Ir : a.Ir);
+  const uint32_t i0 = static_cast<uint32_t>(by) * BN;
+  const int t = threadIdx.x;
+  const int lane = t & 63;
+  const int w = t >> 6;
+  const int c = lane & 15;
+  const int g = lane >> 4;
+
+  // Staging tasks (row, k group), fixed for the workgroup's life:
+  //   X inner: row = id % BF, kg = id / BF;  X lead and L: kg = id % KG, row = id / KG.
+  int xrow[XT], xkg[XT];
+#pragma unroll
+  for (int s = 0; s < XT; ++s) {
+    const int id = t + s * kThreads;
+    xrow[s] = INNER ? id % BF : (id / KG) % BF;
+    xkg[s] = INNER ? (id / BF) % KG : id % KG;
+  }
+
+  // L block -> LDS once (k >= m and rows >= n read as zero).
+  {
+    G lr[LT][KV];
+#pragma unroll
+    for (int s = 0; s < LT; ++s) {
+      const int id = t + s * kThreads;
+      const uint32_t i = i0 + (id / KG) % BN;
+      const int kg = id % KG;
+#pragma unroll
+      for (int e = 0; e < KV; ++e) {
+        const uint32_t k = kg * KV + e;
+        lr[s][e] = (i < n && k < m) ? L[static_cast<int64_t>(i) * a.rs + k * a.cs] : G(0);
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < LT; ++s) {
+      const int id = t + s * kThreads;
+      const int row = id / KG, kg = id % KG;
+      if (row >= BN) continue;
+      if constexpr (SPLIT) {
+        bf16x8_t pl[P];
+#pragma unroll
+        for (int e = 0; e < KV; ++e) {
+          __bf16 o[P];
+          split_bf16<P>(lr[s][e], o);
+#pragma unroll
+          for (int p = 0; p < P; ++p) pl[p][e] = o[p];
+        }
+#pragma unroll
+        for (int p = 0; p < P; ++p) *reinterpret_cast<bf16x8_t*>(&sL[p][row][kg * KV]) = pl[p];
+      } else {
+        FragT f;
+#pragma unroll
+        for (int e = 0; e < KV; ++e) f[e] = lr[s][e];
+        *reinterpret_cast<FragT*>(&sL[0][row][kg * KV]) = f;
+      }
+    }
+  }
+
+  G xr[XT][KV];
+  // Global -> registers for fiber tile bx. Fibers past F are clamped to the
+  // last one (their outputs are never stored); k >= m reads as zero.
+  auto load_x = [&](int64_t bx) {
+    const uint32_t f0 = static_cast<uint32_t>(bx) * BF;
+#pragma unroll
+    for (int s = 0; s < XT; ++s) {
+      uint32_t r = f0 + xrow[s];
+      r = r < F ? r : F - 1;
+      uint32_t base;
+      if constexpr (INNER) {
+        const uint32_t b = r / Il;
+        base = (r - b * Il) + Il * m * b;
+      } else {
+        base = r * m;
+      }
+      const uint32_t kb = xkg[s] * KV;
+      if constexpr (VEC) {
+        if (kb < m) {
+          const GV v = *reinterpret_cast<const GV*>(X + base + kb);
+#pragma unroll
+          for (int e = 0; e < KV; ++e) xr[s][e] = v[e];
+        } else {
+#pragma unroll
+          for (int e = 0; e < KV; ++e) xr[s][e] = G(0);
+        }
+      } else {
+        const uint32_t ks = INNER ? Il : 1;
+#pragma unroll
+        for (int e = 0; e < KV; ++e) {
+          const uint32_t k = kb + e;
+          xr[s][e] = k < m ? X[base + k * ks] : G(0);
+        }
+      }
+    }
+  };
+  auto store_x = [&](int buf) {
+#pragma unroll
+    for (int s = 0; s < XT; ++s) {
+      const int id = t + s * kThreads;
+      if (id >= BF * KG) continue;
+      const int row = xrow[s], kg = xkg[s];
+      if constexpr (SPLIT) {
+        bf16x8_t pl[P];
+#pragma unroll
+        for (int e = 0; e < KV; ++e) {
+          __bf16 o[P];
+          split_bf16<P>(xr[s][e], o);
+#pragma unroll
+          for (int p = 0; p < P; ++p) pl[p][e] = o[p];
+        }
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+          *reinterpret_cast<bf16x8_t*>(&sX[buf][p][row][kg * KV]) = pl[p];
+      } else {
+        FragT f;
+#pragma unroll
+        for (int e = 0; e < KV; ++e) f[e] = xr[s][e];
+        *reinterpret_cast<FragT*>(&sX[buf][0][row][kg * KV]) = f;
+      }
+    }
+  };
+
+  if (t0 < ntiles) {
+    load_x(t0);
+    store_x(0);
+  }
+  __syncthreads();
+  int buf = 0;
+  for (int64_t bx = t0; bx < ntiles; bx += tstep, buf ^= 1) {
+    const int64_t nx = bx + tstep;
+    if (nx < ntiles) load_x(nx);
+    acc_t hi[QB][PB], lo[QB][PB];
+#pragma unroll
+    for (int q = 0; q < QB; ++q)
+#pragma unroll
+      for (int p = 0; p < PB; ++p) {
+        hi[q][p] = acc_t{};
+        lo[q][p] = acc_t{};
+      }
+#pragma unroll
+    for (int kk = 0; kk < KP; kk += MK) {
+      FragT xa[FB][P];
+#pragma unroll
+      for (int fb = 0; fb < FB; ++fb)
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+          xa[fb][p] = *reinterpret_cast<const FragT*>(
+              &sX[buf][p][w * 16 * FB + fb * 16 + c][kk + KV * g]);
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        FragT la[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+          la[p] = *reinterpret_cast<const FragT*>(&sL[p][nb * 16 + c][kk + KV * g]);
+#pragma unroll
+        for (int fb = 0; fb < FB; ++fb) {
+          if constexpr (INNER)
+            macro_step<FORM>(la, xa[fb], hi[nb][fb], lo[nb][fb]);
+          else
+            macro_step<FORM>(xa[fb], la, hi[fb][nb], lo[fb][nb]);
+        }
+      }
+    }
+    // outputs of this tile (MFMA column = memory-contiguous index)
+    const uint32_t f0 = static_cast<uint32_t>(bx) * BF;
+#pragma unroll
+    for (int q = 0; q < QB; ++q)
+#pragma unroll
+      for (int p = 0; p < PB; ++p) {
+        acc_t val = hi[q][p];
+        if constexpr (SPLIT) val = hi[q][p] + lo[q][p];
+        if constexpr (INNER) {
+          const uint32_t r = f0 + w * 16 * FB + p * 16 + c;
+          if (r >= F) continue;
+          const uint32_t b = r / Il;
+          G* yb = Y + ((r - b * Il) + Il * n * b);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const uint32_t i = i0 + q * 16 + FT::row(lane, v);
+            if (i < n) {
+              G* dst = yb + Il * i;
+              *dst = a.accumulate ? *dst + val[v] : val[v];
+            }
+          }
+        } else {
+          const uint32_t i = i0 + p * 16 + c;
+          if (i >= n) continue;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const uint32_t f = f0 + w * 16 * FB + q * 16 + FT::row(lane, v);
+            if (f < F) {
+              G* dst = Y + (i + n * f);
+              *dst = a.accumulate ? *dst + val[v] : val[v];
+            }
+          }
+        }
+      }
+    if (nx < ntiles) store_x(buf ^ 1);
+    __syncthreads();
+  }
+}
+
+}  // namespace tile
+}  // namespace kp

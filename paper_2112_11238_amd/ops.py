@@ -338,6 +338,7 @@ class BatchedTucker:
         return self.S
 
 
-def force_tile(nb=0, fb=0, bk=0, occ=0, pf=0):
-    """Force the mode-kernel tile for later launches (nb=0 resets)."""
-    check(lib().kp_force_tile(nb, fb, bk, occ, pf), "kp_force_tile")
+def force_tile(nb=0, fb=0, bk=0, occ=0, pf=0, kind=0):
+    """Force the mode-kernel tile for later launches (nb=0 resets); kind 1
+    selects a strip tile (bk = padded contraction length >= m)."""
+    check(lib().kp_force_tile(nb, fb, bk, occ, pf, kind), "kp_force_tile")

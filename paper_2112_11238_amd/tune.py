@@ -29,7 +29,7 @@ from .ops import _canon, _mdesc, _mlist, _prec, _tdesc, check, force_tile, lib, 
 
 FORMS = {"f64": 0, "f32": 1, "bf16x3": 3, "bf16x6": 6}
 FORM_NAMES = {v: k for k, v in FORMS.items()}
-_FIELDS = ("form", "Il", "m", "n", "Ir", "nb", "fb", "bk", "occ", "pf")
+_FIELDS = ("form", "Il", "m", "n", "Ir", "nb", "fb", "bk", "occ", "pf", "kind")
 
 
 def form_code(dtype, prec="native"):
@@ -50,15 +50,19 @@ def _entry_dict(e):
     return {k: int(getattr(e, k)) for k in _FIELDS}
 
 
-def variants(form, batch=False):
-    """Compiled tiles (nb, fb, bk, occ, pf) of a form: the standalone mode
-    kernels, or the batched executor's (occ and pf 0 there)."""
+def variants(form, batch=False, m=None):
+    """Compiled tiles (nb, fb, bk, occ, pf, kind) of a form: the standalone
+    kernels, or the batched executor's. With `m`, only the tiles that can run
+    a contraction of that length (strip tiles need m <= bk)."""
     form = FORMS.get(form, form)
     n = lib().kp_tile_variants(form, int(bool(batch)), None, 0)
     check(min(n, 0), "kp_tile_variants")
-    buf = (ctypes.c_int32 * (5 * max(n, 1)))()
+    buf = (ctypes.c_int32 * (6 * max(n, 1)))()
     lib().kp_tile_variants(form, int(bool(batch)), buf, n)
-    return [tuple(buf[5 * i:5 * i + 5]) for i in range(n)]
+    out = [tuple(buf[6 * i:6 * i + 6]) for i in range(n)]
+    if m is not None:
+        out = [v for v in out if v[5] == 0 or m <= v[2]]
+    return out
 
 
 def entries():
@@ -74,12 +78,12 @@ def clear():
 
 
 def set_tile(form, Il, m, n, Ir, tile):
-    """Record `tile` = (nb, fb, bk[, occ, pf]) for one product view."""
-    t = tuple(tile) + (0,) * (5 - len(tile))
+    """Record `tile` = (nb, fb, bk[, occ, pf, kind]) for one product view."""
+    t = tuple(tile) + (0,) * (6 - len(tile))
     e = _lib.KpTuneEntry()
     e.form = FORMS.get(form, form)
     e.Il, e.m, e.n, e.Ir = Il, m, n, Ir
-    e.nb, e.fb, e.bk, e.occ, e.pf = t
+    e.nb, e.fb, e.bk, e.occ, e.pf, e.kind = t
     check(lib().kp_tune_set(ctypes.byref(e)), "kp_tune_set")
 
 
@@ -88,7 +92,7 @@ def lookup(form, Il, m, n, Ir):
     e = _lib.KpTuneEntry()
     st = lib().kp_tune_lookup(FORMS.get(form, form), Il, m, n, Ir, ctypes.byref(e))
     check(min(st, 0), "kp_tune_lookup")
-    return bool(st), (e.nb, e.fb, e.bk, e.occ, e.pf)
+    return bool(st), (e.nb, e.fb, e.bk, e.occ, e.pf, e.kind)
 
 
 def save(path):
@@ -102,7 +106,7 @@ def load(path):
         rec = json.load(fh)
     for e in rec["entries"]:
         set_tile(e["form"], e["Il"], e["m"], e["n"], e["Ir"],
-                 (e["nb"], e["fb"], e["bk"], e["occ"], e["pf"]))
+                 (e["nb"], e["fb"], e["bk"], e["occ"], e["pf"], e.get("kind", 0)))
     return len(rec["entries"])
 
 
@@ -158,7 +162,7 @@ def tune_view(dtype, prec, Il, m, n, Ir, objective="latency", reps=10, fill_fibe
     as (tile, seconds per original view, {tile: seconds})."""
     form = form_code(dtype, prec)
     batch = objective == "throughput"
-    cands = variants(form, batch=batch)
+    cands = variants(form, batch=batch, m=m)
     rep_Ir, scale = Ir, 1
     if batch:
         es = torch.empty((), dtype=dtype).element_size()

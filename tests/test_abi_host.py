@@ -208,9 +208,10 @@ def test_expm_argument_errors(lib):
 
 
 def test_force_tile_argument_errors(lib):
-    assert lib.kp_force_tile(4, 0, 16, 0, 0) == -9
-    assert lib.kp_force_tile(4, 1, 16, 0, 3) == -9
-    assert lib.kp_force_tile(0, 0, 0, 0, 0) == 0
+    assert lib.kp_force_tile(4, 0, 16, 0, 0, 0) == -9
+    assert lib.kp_force_tile(4, 1, 16, 0, 3, 0) == -9
+    assert lib.kp_force_tile(4, 1, 16, 0, 0, 2) == -9
+    assert lib.kp_force_tile(0, 0, 0, 0, 0, 0) == 0
 
 
 def test_workspace_sizes(lib, L):

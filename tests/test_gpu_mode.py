@@ -149,6 +149,45 @@ def test_every_tile_variant(kp, dt, prec):
         kp.force_tile(0)
 
 
+def strip_cases(kp_len):
+    """(torch shape, mode, layout) cases for a strip of padded length kp_len:
+    the lead layout with m = kp_len (16-byte loads) and with a k tail, the
+    innermost-strided layout and a middle mode; enough fibers that every
+    workgroup streams several tiles."""
+    m = kp_len
+    return [((150001, m), 2, "lead"), ((150001, m - 3), 2, "lead tail"),
+            ((m - 1, 300, 500), 1, "inner"), ((40, m, 3750), 2, "middle")]
+
+
+@pytest.mark.parametrize("dt,prec", FORMS)
+def test_every_strip_variant(kp, dt, prec):
+    from paper_2112_11238_amd import tune
+    form = tune.form_code(DT[dt], prec)
+    strips = [v for v in tune.variants(form) if v[5] == 1]
+    assert strips
+    rng = np.random.default_rng(77)
+    try:
+        for tile in strips:
+            nb, fb, klen = tile[0], tile[1], tile[2]
+            n = 16 * nb * 2 + 5            # three n blocks, the last one ragged
+            for shape, mu, what in strip_cases(klen):
+                T = rng.standard_normal(shape)
+                Lm = rng.standard_normal((n, shape[mu - 1]))
+                T64, L64 = cast64(T, DT[dt]), cast64(Lm, DT[dt])
+                say("strip", tile, dt, prec, shape, mu, what)
+                kp.force_tile(*tile)
+                S = kp.mump(to_dev(T, DT[dt]), to_dev(Lm, DT[dt]), mu, prec=prec)
+                torch.cuda.synchronize()
+                kp.force_tile(0)
+                ref = oracle.mump(T64, L64, mu)
+                f = [None] * len(shape)
+                f[mu - 1] = L64
+                bound = chain_bound(T64, f, prec, DT[dt])
+                assert np.all(np.abs(S.double().cpu().numpy() - ref) <= bound), (tile, what)
+    finally:
+        kp.force_tile(0)
+
+
 TUCKER_CASES = [
     ((50, 50), (50, 50)),
     ((4, 5, 6), (7, 3, 9)),

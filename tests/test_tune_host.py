@@ -35,7 +35,8 @@ def tune(lib):
 def entry(L, form, Il, m, n, Ir, tile):
     e = L.KpTuneEntry()
     e.form, e.Il, e.m, e.n, e.Ir = form, Il, m, n, Ir
-    e.nb, e.fb, e.bk, e.occ, e.pf = tile
+    t = tuple(tile) + (0,) * (6 - len(tile))
+    e.nb, e.fb, e.bk, e.occ, e.pf, e.kind = t
     return e
 
 
@@ -49,8 +50,13 @@ def test_variant_lists(lib, tune):
         # every tile of the batched executor has a standalone kernel with the
         # same (nb, fb, bk): the throughput tuner times it there
         for v in tune.variants(form, batch=True):
-            assert v[3:] == (0, 0)
-            assert any(w[:3] == v[:3] for w in mode), (form, v)
+            assert v[3:] == (0, 0, 0)
+            assert any(w[:3] == v[:3] and w[5] == 0 for w in mode), (form, v)
+        # strip tiles (kind 1): occ = pf = 0, bk the padded contraction length
+        strips = [v for v in mode if v[5] == 1]
+        assert strips and all(v[3:5] == (0, 0) and v[2] in (16, 32, 64) for v in strips)
+        assert all(v[5] == 0 or v[2] >= 40 for v in tune.variants(form, m=40))
+        assert len(tune.variants(form, m=200)) == len(mode) - len(strips)
     assert lib.kp_tile_variants(2, 0, None, 0) == -9
     assert lib.kp_tile_variants(0, 2, None, 0) == -9
     assert lib.kp_tile_variants(0, 0, None, 5) == -1
@@ -62,15 +68,23 @@ def test_set_lookup_list_clear(lib, L, tune):
     assert lib.kp_tune_set(ctypes.byref(entry(L, 0, 0, 8, 8, 8, (4, 1, 16, 0, 0)))) == -9
     assert lib.kp_tune_set(ctypes.byref(entry(L, 0, 1, 8, 8, 8, (5, 1, 16, 0, 0)))) == -9
     assert lib.kp_tune_set(ctypes.byref(entry(L, 0, 1, 8, 8, 8, (4, 1, 16, 0, 3)))) == -9
+    assert lib.kp_tune_set(ctypes.byref(entry(L, 1, 1, 40, 8, 8, (2, 2, 32, 0, 0, 1)))) == -9
+    assert lib.kp_tune_set(ctypes.byref(entry(L, 1, 1, 8, 8, 8, (2, 2, 32, 0, 0, 2)))) == -9
     assert lib.kp_tune_count() == 0
+    # short contractions default to a strip tile covering m
+    tuned, tile = tune.lookup("f32", 7, 24, 40, 9)
+    assert not tuned and tile[5] == 1 and tile[2] >= 24 and 16 * tile[0] >= 32
+    tune.set_tile("f32", 7, 24, 40, 9, (1, 2, 32, 0, 0, 1))
+    assert tune.lookup("f32", 7, 24, 40, 9) == (True, (1, 2, 32, 0, 0, 1))
+    tune.clear()
     # default first
     tuned, tile = tune.lookup("f64", 40, 200, 200, 200)
     assert not tuned and tile[:3] == (7, 1, 16)
     tune.set_tile("f64", 40, 200, 200, 200, (4, 1, 16))
     tuned, tile = tune.lookup("f64", 40, 200, 200, 200)
-    assert tuned and tile[:3] == (4, 1, 16) and tile[3] > 0 and tile[4] == 1  # resolved
+    assert tuned and tile[:3] == (4, 1, 16) and tile[3] > 0 and tile[4:] == (1, 0)  # resolved
     tune.set_tile("f64", 40, 200, 200, 200, (7, 1, 8, 2, 2))     # replace
-    assert tune.lookup("f64", 40, 200, 200, 200) == (True, (7, 1, 8, 2, 2))
+    assert tune.lookup("f64", 40, 200, 200, 200) == (True, (7, 1, 8, 2, 2, 0))
     assert tune.lookup("f32", 40, 200, 200, 200)[0] is False      # the form is in the key
     assert tune.lookup("f64", 41, 200, 200, 200)[0] is False
     tune.set_tile("bf16x3", 1, 30, 20, 1000, (2, 2, 32))
