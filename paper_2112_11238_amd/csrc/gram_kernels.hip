@@ -12,6 +12,10 @@
 // its share of fiber chunks with MFMA, writes the partial tile to a workspace,
 // and a second kernel adds the shares in a fixed order (deterministic) and
 // writes dL with its own strides.
+#include <mutex>
+#include <unordered_map>
+
+#include "gram_strip.h"
 #include "gram_tile.h"
 #include "kp_common.h"
 #include "kp_internal.h"
@@ -27,20 +31,80 @@ __global__ __launch_bounds__(kThreads, 2) void gram_kernel(GramArgs g) {
   gram_tile<E, BR, INNER>(g, blockIdx.x, blockIdx.y, blockIdx.z, lds);
 }
 
-// dL(i, j) = sum_s part[s][i][j], written at dL[i*rs + j*cs].
+// dL(i, j) = sum_s part[s][i][j] in a fixed order, written at dL[i*rs + j*cs];
+// workgroup x handles outputs 16x .. 16x + 15.
 template <typename E>
 __global__ __launch_bounds__(kThreads) void gram_reduce(const E* __restrict__ part, int64_t splits,
                                                         int64_t n, int64_t m, E* __restrict__ dL,
                                                         int64_t rs, int64_t cs) {
-  const int64_t idx = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
-  if (idx >= n * m) return;
-  const int64_t i = idx / m, j = idx - (idx / m) * m;
-  E s = E(0);
-  for (int64_t k = 0; k < splits; ++k) s += part[k * n * m + idx];
-  dL[i * rs + j * cs] = s;
+  __shared__ E sred[kThreads];
+  gram_reduce_block<E>(part, splits, n, m, dL, rs, cs, blockIdx.x, sred);
 }
 
 constexpr int kBR = 32;
+
+// Small factors (n, m <= 64): one partial tile per workgroup, each
+// workgroup streaming a contiguous run of fiber chunks (gram_strip.h).
+template <typename E>
+constexpr int strip_br() { return sizeof(E) == 8 ? 32 : 64; }
+constexpr int64_t kMaxStripSplits = 2048;
+
+template <typename E, int NB, int MB, bool INNER>
+__global__ __launch_bounds__(kThreads, 2) void gram_strip_kernel(GramArgs g, int64_t chunks,
+                                                                 int64_t splits) {
+  constexpr int BR = strip_br<E>();
+  __shared__ __attribute__((aligned(16))) char lds[strip_lds_bytes<E, NB, MB, BR>()];
+  const int64_t s = blockIdx.x;
+  const int64_t cb = s * chunks / splits, ce = (s + 1) * chunks / splits;
+  gram_strip<E, NB, MB, BR, INNER>(g, cb, ce, static_cast<E*>(g.part) + s * g.n * g.m, lds);
+}
+
+using StripGramFn = void (*)(GramArgs, int64_t, int64_t);
+
+template <typename E>
+StripGramFn strip_gram_fn(int64_t n, int64_t m, bool inner) {
+  const bool n2 = n <= 32, m2 = m <= 32;
+  if (inner) {
+    if (n2) return m2 ? gram_strip_kernel<E, 2, 2, true> : gram_strip_kernel<E, 2, 4, true>;
+    return m2 ? gram_strip_kernel<E, 4, 2, true> : gram_strip_kernel<E, 4, 4, true>;
+  }
+  if (n2) return m2 ? gram_strip_kernel<E, 2, 2, false> : gram_strip_kernel<E, 2, 4, false>;
+  return m2 ? gram_strip_kernel<E, 4, 2, false> : gram_strip_kernel<E, 4, 4, false>;
+}
+
+bool use_strip(int64_t Il, int64_t n, int64_t m, int64_t Ir, size_t esize) {
+  const int64_t rows = n > m ? n : m;
+  return n <= 64 && m <= 64 &&
+         Il * Ir * rows * static_cast<int64_t>(esize) < (static_cast<int64_t>(1) << 31);
+}
+
+int64_t strip_chunks(int64_t Il, int64_t Ir, size_t esize) {
+  const int64_t br = esize == 8 ? 32 : 64;
+  return (Il * Ir + br - 1) / br;
+}
+
+int strip_slots(StripGramFn fn) {
+  static std::mutex mu;
+  static std::unordered_map<const void*, int> cache;
+  std::lock_guard<std::mutex> lock(mu);
+  const auto it = cache.find(reinterpret_cast<const void*>(fn));
+  int nb = 1;
+  if (it != cache.end()) {
+    nb = it->second;
+  } else {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(fn),
+                                                     kThreads, 0) != hipSuccess ||
+        nb < 1)
+      nb = 1;
+    cache[reinterpret_cast<const void*>(fn)] = nb;
+  }
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus < 1)
+    cus = 256;
+  return nb * cus;
+}
 
 }  // namespace
 
@@ -55,6 +119,12 @@ int64_t gram_splits(int64_t Il, int64_t n, int64_t m, int64_t Ir) {
 }
 
 size_t gram_workspace(int64_t Il, int64_t n, int64_t m, int64_t Ir, size_t esize) {
+  if (use_strip(Il, n, m, Ir, esize)) {
+    int64_t s = strip_chunks(Il, Ir, esize);
+    if (s > kMaxStripSplits) s = kMaxStripSplits;
+    if (s < 1) s = 1;
+    return static_cast<size_t>(s * n * m) * esize;
+  }
   return static_cast<size_t>(gram_splits(Il, n, m, Ir) * n * m) * esize;
 }
 
@@ -62,6 +132,40 @@ hipError_t launch_gram(int dtype, const void* Q, const void* P, int64_t Il, int6
                        int64_t Ir, void* part, void* dL, int64_t rs, int64_t cs,
                        hipStream_t stream) {
   if (n == 0 || m == 0) return hipSuccess;
+  const size_t es = dtype == KP_F64 ? 8 : 4;
+  const int64_t total = n * m;
+  const unsigned rblocks = static_cast<unsigned>((total + 15) / 16);
+  if (use_strip(Il, n, m, Ir, es)) {
+    GramArgs g{};
+    g.Q = Q;
+    g.P = P;
+    g.part = part;
+    g.Il = Il;
+    g.n = n;
+    g.m = m;
+    g.Ir = Ir;
+    const bool inner = Il > 1;
+    const int64_t chunks = strip_chunks(Il, Ir, es);
+    const StripGramFn fn = dtype == KP_F64 ? strip_gram_fn<double>(n, m, inner)
+                                           : strip_gram_fn<float>(n, m, inner);
+    int64_t splits = strip_slots(fn);
+    if (splits > chunks) splits = chunks;
+    if (splits > kMaxStripSplits) splits = kMaxStripSplits;
+    if (splits < 1) splits = 1;
+    hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>(splits)), dim3(kThreads), 0, stream, g,
+                       chunks, splits);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (dtype == KP_F64)
+      hipLaunchKernelGGL(gram_reduce<double>, dim3(rblocks), dim3(kThreads), 0, stream,
+                         static_cast<const double*>(part), splits, n, m, static_cast<double*>(dL),
+                         rs, cs);
+    else
+      hipLaunchKernelGGL(gram_reduce<float>, dim3(rblocks), dim3(kThreads), 0, stream,
+                         static_cast<const float*>(part), splits, n, m, static_cast<float*>(dL),
+                         rs, cs);
+    return hipGetLastError();
+  }
   GramArgs g;
   g.Q = Q;
   g.P = P;
@@ -90,14 +194,12 @@ hipError_t launch_gram(int dtype, const void* Q, const void* P, int64_t Il, int6
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int64_t total = n * m;
-  const unsigned blocks = static_cast<unsigned>((total + kThreads - 1) / kThreads);
   if (dtype == KP_F64)
-    hipLaunchKernelGGL(gram_reduce<double>, dim3(blocks), dim3(kThreads), 0, stream,
+    hipLaunchKernelGGL(gram_reduce<double>, dim3(rblocks), dim3(kThreads), 0, stream,
                        static_cast<const double*>(part), splits, n, m, static_cast<double*>(dL),
                        rs, cs);
   else
-    hipLaunchKernelGGL(gram_reduce<float>, dim3(blocks), dim3(kThreads), 0, stream,
+    hipLaunchKernelGGL(gram_reduce<float>, dim3(rblocks), dim3(kThreads), 0, stream,
                        static_cast<const float*>(part), splits, n, m, static_cast<float*>(dL), rs,
                        cs);
   return hipGetLastError();

@@ -1,0 +1,231 @@
+// Factor-gradient contraction for small factors (n, m <= 64):
+// C(i, j) = sum over fibers r of Q(r, i) P(r, j), Q viewed as (Il, n, Ir),
+// P as (Il, m, Ir), r = a + Il*b (the rule is derived from the Kronecker
+// form of the Tucker operator, Sec. 2, and the transpose rule of
+// Appendix A, property 5).
+//
+// The whole n x m output fits one workgroup's registers, so a workgroup
+// streams a contiguous run of BR-fiber chunks: both operands of a chunk go
+// through double-buffered LDS with the next chunk's global loads in flight,
+// and the four waves split each chunk's fibers (the MFMA k dimension), each
+// accumulating the full output. At the end the waves' partial sums are
+// added in LDS in a fixed order and written as this workgroup's partial
+// tile; a separate pass adds the workgroups' tiles in a fixed order.
+#pragma once
+
+#include "gram_tile.h"
+
+namespace kp {
+namespace gram {
+
+template <typename E, int NB, int MB, int BR>
+constexpr size_t strip_lds_bytes() {
+  constexpr size_t stage = 2 * static_cast<size_t>(16 * (NB + MB)) * (BR + 16 / sizeof(E)) * sizeof(E);
+  constexpr size_t reduce = static_cast<size_t>(16 * NB) * (16 * MB) * sizeof(E);
+  return stage > reduce ? stage : reduce;
+}
+
+// Chunks [c_begin, c_end) of BR consecutive fibers; writes the partial n x m
+// tile to out[i*m + j]. At the end the waves' sums are added in LDS in
+// wave order, ((w0 + w1) + w2) + w3.
+// INNER (Il > 1): a staging task is one fiber and KV consecutive rows, lanes
+// walk along fibers (contiguous in memory). Lead (Il == 1): a task is one
+// row and KV consecutive fibers, lanes walk along rows.
+template <typename E, int NB, int MB, int BR, bool INNER>
+__device__ __forceinline__ void gram_strip(const GramArgs& g, int64_t c_begin, int64_t c_end,
+                                           E* __restrict__ out, char* __restrict__ lds) {
+  using GT = GramT<E>;
+  using frag = typename GT::frag;
+  using acc_t = typename GT::acc_t;
+  constexpr int KV = GT::KV;
+  constexpr int MK = 4 * KV;
+  constexpr int RQ = 16 * NB, RP = 16 * MB;      // staged rows of Q and P
+  constexpr int LDR = BR + 16 / sizeof(E);
+  constexpr int KW = BR / 4;                     // fibers per wave and chunk
+  static_assert(KW % MK == 0, "each wave needs whole macro steps");
+  // tasks: INNER (fiber, row group of KV), lead (row, fiber group of KV)
+  constexpr int TQ = (RQ / KV) * BR;
+  constexpr int TP = (RP / KV) * BR;
+  constexpr int NQ = (TQ + kThreads - 1) / kThreads;
+  constexpr int NP = (TP + kThreads - 1) / kThreads;
+  typedef E QTile[RQ][LDR];
+  typedef E PTile[RP][LDR];
+  QTile* sQ = reinterpret_cast<QTile*>(lds);
+  PTile* sP = reinterpret_cast<PTile*>(lds + 2 * sizeof(QTile));
+
+  const E* __restrict__ Q = static_cast<const E*>(g.Q);
+  const E* __restrict__ P = static_cast<const E*>(g.P);
+  // 32-bit index math: the host keeps each operand below 2^31 bytes
+  const uint32_t Il = static_cast<uint32_t>(g.Il), n = static_cast<uint32_t>(g.n);
+  const uint32_t m = static_cast<uint32_t>(g.m);
+  const uint32_t F = static_cast<uint32_t>(g.Il * g.Ir);
+  const int t = threadIdx.x;
+  const int lane = t & 63;
+  const int w = t >> 6;
+  const int c = lane & 15;
+  const int gq = lane >> 4;
+
+  E qv[NQ][KV], pv[NP][KV];
+  // offset of element (fiber r, row i) of a view with `len` rows
+  auto offset = [&](uint32_t r, uint32_t i, uint32_t len) -> uint32_t {
+    if constexpr (INNER) {
+      const uint32_t b = r / Il;
+      return (r - b * Il) + Il * (i + len * b);
+    } else {
+      return i + len * r;
+    }
+  };
+  auto load = [&](int64_t ch) {
+    const uint32_t r0 = static_cast<uint32_t>(ch) * BR;
+#pragma unroll
+    for (int s = 0; s < NQ; ++s) {
+      const int id = t + s * kThreads;
+      const int fr = INNER ? id % BR : (id / RQ) * KV;   // first fiber of the task
+      const int row = INNER ? (id / BR) * KV : id % RQ;  // first row of the task
+#pragma unroll
+      for (int e = 0; e < KV; ++e) {
+        const uint32_t r = r0 + fr + (INNER ? 0 : e);
+        const uint32_t i = row + (INNER ? e : 0);
+        const bool ok = id < TQ && r < F && i < n;
+        const E v = Q[ok ? offset(r, i, n) : 0];
+        qv[s][e] = ok ? v : E(0);
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < NP; ++s) {
+      const int id = t + s * kThreads;
+      const int fr = INNER ? id % BR : (id / RP) * KV;
+      const int row = INNER ? (id / BR) * KV : id % RP;
+#pragma unroll
+      for (int e = 0; e < KV; ++e) {
+        const uint32_t r = r0 + fr + (INNER ? 0 : e);
+        const uint32_t j = row + (INNER ? e : 0);
+        const bool ok = id < TP && r < F && j < m;
+        const E v = P[ok ? offset(r, j, m) : 0];
+        pv[s][e] = ok ? v : E(0);
+      }
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int s = 0; s < NQ; ++s) {
+      const int id = t + s * kThreads;
+      if (id >= TQ) continue;
+      if constexpr (INNER) {
+        const int fr = id % BR, row = (id / BR) * KV;
+#pragma unroll
+        for (int e = 0; e < KV; ++e) sQ[buf][row + e][fr] = qv[s][e];
+      } else {
+        const int fr = (id / RQ) * KV, row = id % RQ;
+        frag f;
+#pragma unroll
+        for (int e = 0; e < KV; ++e) f[e] = qv[s][e];
+        *reinterpret_cast<frag*>(&sQ[buf][row][fr]) = f;
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < NP; ++s) {
+      const int id = t + s * kThreads;
+      if (id >= TP) continue;
+      if constexpr (INNER) {
+        const int fr = id % BR, row = (id / BR) * KV;
+#pragma unroll
+        for (int e = 0; e < KV; ++e) sP[buf][row + e][fr] = pv[s][e];
+      } else {
+        const int fr = (id / RP) * KV, row = id % RP;
+        frag f;
+#pragma unroll
+        for (int e = 0; e < KV; ++e) f[e] = pv[s][e];
+        *reinterpret_cast<frag*>(&sP[buf][row][fr]) = f;
+      }
+    }
+  };
+
+  acc_t acc[NB][MB];
+#pragma unroll
+  for (int a = 0; a < NB; ++a)
+#pragma unroll
+    for (int b = 0; b < MB; ++b) acc[a][b] = acc_t{};
+  // row blocks past n / column blocks past m hold no output: skip them
+  const int nbu = static_cast<int>((n + 15) / 16), mbu = static_cast<int>((m + 15) / 16);
+
+  if (c_begin < c_end) {
+    load(c_begin);
+    store(0);
+  }
+  __syncthreads();
+  int buf = 0;
+  for (int64_t ch = c_begin; ch < c_end; ++ch, buf ^= 1) {
+    if (ch + 1 < c_end) load(ch + 1);
+#pragma unroll
+    for (int kk = w * KW; kk < (w + 1) * KW; kk += MK) {
+      frag fa[NB], fb[MB];
+#pragma unroll
+      for (int a = 0; a < NB; ++a)
+        if (a < nbu) fa[a] = *reinterpret_cast<const frag*>(&sQ[buf][a * 16 + c][kk + KV * gq]);
+#pragma unroll
+      for (int b = 0; b < MB; ++b)
+        if (b < mbu) fb[b] = *reinterpret_cast<const frag*>(&sP[buf][b * 16 + c][kk + KV * gq]);
+#pragma unroll
+      for (int a = 0; a < NB; ++a)
+#pragma unroll
+        for (int b = 0; b < MB; ++b)
+          if (a < nbu && b < mbu) GT::step(fa[a], fb[b], acc[a][b]);
+    }
+    if (ch + 1 < c_end) store(buf ^ 1);
+    __syncthreads();
+  }
+
+  // wave sums added into one LDS tile in wave order
+  typedef E Red[RQ][RP];
+  Red& red = *reinterpret_cast<Red*>(lds);
+  for (int ww = 0; ww < 4; ++ww) {
+    if (w == ww) {
+#pragma unroll
+      for (int a = 0; a < NB; ++a)
+#pragma unroll
+        for (int b = 0; b < MB; ++b)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            E& dst = red[a * 16 + GT::row(lane, v)][b * 16 + c];
+            dst = ww == 0 ? acc[a][b][v] : dst + acc[a][b][v];
+          }
+    }
+    __syncthreads();
+  }
+  for (int idx = t; idx < RQ * RP; idx += kThreads) {
+    const int i = idx / RP, j = idx % RP;
+    if (static_cast<uint32_t>(i) < n && static_cast<uint32_t>(j) < m) out[i * m + j] = red[i][j];
+  }
+  __syncthreads();  // the caller may reuse the LDS
+}
+
+// part holds `splits` partial n x m tiles; dL(i, j) = their sum in split
+// order, written at dL[i*rs + j*cs]. A workgroup handles 16 outputs with 16
+// threads each: thread q adds splits q, q + 16, ... and the 16 partial sums
+// are then added in q order.
+template <typename E>
+__device__ __forceinline__ void gram_reduce_block(const E* __restrict__ part, int64_t splits,
+                                                  int64_t n, int64_t m, E* __restrict__ dL,
+                                                  int64_t rs, int64_t cs, int64_t blk,
+                                                  E* __restrict__ sred) {
+  const int t = threadIdx.x;
+  const int o = t & 15, q = t >> 4;
+  const int64_t idx = blk * 16 + o;
+  const int64_t nm = n * m;
+  E s = E(0);
+  if (idx < nm)
+    for (int64_t k = q; k < splits; k += 16) s += part[k * nm + idx];
+  sred[q * 16 + o] = s;
+  __syncthreads();
+  if (q == 0 && idx < nm) {
+    E tot = sred[o];
+    for (int k = 1; k < 16; ++k) tot += sred[k * 16 + o];
+    const int64_t i = idx / m, j = idx - (idx / m) * m;
+    dL[i * rs + j * cs] = tot;
+  }
+  __syncthreads();
+}
+
+}  // namespace gram
+}  // namespace kp

@@ -18,6 +18,8 @@ CASES = [
     ((3, 1, 4, 9), (2, 5, 4, 3)),
     ((40, 33, 3), (17, 70, 5)),
     ((4, 4, 4, 4, 4, 4), (6, 6, 6, 6, 6, 6)),
+    # tens of thousands of fibers per factor gradient: several chunks per workgroup
+    ((60, 50, 40, 30), (20, 64, 33, 9)),
 ]
 
 
