@@ -153,12 +153,14 @@ int kp_tucker_backward(const kp_tensor* G, const kp_tensor* T,
 /* ---- batched Tucker operator: persistent launches per dependency level -----
  * `count` independent problems of any orders and sizes (same dtype), each a
  * Tucker operator in definition order (Sec. 2) and optionally its gradient.
- * All tiles of all problems that sit at the same dependency level (the
- * forward product of mode s, a factor-gradient partial sum, ...) run in ONE
- * persistent launch; consecutive levels are consecutive launches on
+ * All tasks of all problems that sit at the same dependency level (the
+ * forward product of mode s, a factor-gradient partial sum, ...) and share
+ * a task type (tile or strip variant, gram, reduce) run in ONE persistent
+ * launch of a kernel compiled for that type; levels are launched in order on
  * `stream`, so no workgroup waits for another. A forward pass of order-d
- * problems takes d launches, forward plus backward about 2d + 2; a HIP graph
- * capturing kp_tucker_batched replays the whole batch.
+ * problems takes d levels, forward plus backward about d + 2 (the reverse
+ * sweep does not wait for the forward); a HIP graph capturing
+ * kp_tucker_batched replays the whole batch.
  * Per problem: S = T x_1 L[0] ... x_d L[d-1] (no identity factors here).
  * If G.data != NULL the backward runs too: dT (if dT.data != NULL) and every
  * dL[k] with dL[k].data != NULL, as kp_tucker_backward defines them; the
@@ -177,7 +179,8 @@ int kp_tucker_backward(const kp_tensor* G, const kp_tensor* T,
  * Errors: KP_ERR_NULL, KP_ERR_ORDER, KP_ERR_DTYPE, KP_ERR_SHAPE (mismatched
  * sizes, NULL or identity factors, a tensor of 2^31 bytes or more),
  * KP_ERR_WORKSPACE (ws or plan too small, or ws not the planned one),
- * KP_ERR_VALUE (count < 0, plan bytes not a plan). */
+ * KP_ERR_VALUE (count < 0, plan bytes not a plan or with an inconsistent
+ * launch group). */
 typedef struct {
   kp_tensor T, S;
   kp_matrix L[KP_MAX_ORDER];

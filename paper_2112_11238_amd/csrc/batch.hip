@@ -1,37 +1,51 @@
 // Batched Tucker operator: many independent problems (uneven sizes), forward
-// and optionally backward, in a few persistent launches.
+// and optionally backward, in a few launches.
 //
 // Every mu-mode product, factor-gradient partial sum and partial-sum
-// reduction of every problem is a "stage" made of independent tiles. A
+// reduction of every problem is a "stage" made of independent tasks. A
 // stage's level is one more than the deepest level among the stages it
 // depends on (the forward product of mode s depends on mode s-1, a factor
-// gradient on the forward partial and on the reverse sweep, ...). All stages
-// of one level, across all problems, run in ONE persistent launch whose
-// workgroups stride over the level's tiles; the next level is the next launch
-// on the same stream, so kernel boundaries order the dependencies and no
-// workgroup ever waits for another. A forward pass of order-d problems takes
-// d launches; with the backward about 2d + 2. Capturing kp_tucker_batched in
-// a HIP graph turns the whole batch into one graph of that many nodes.
+// gradient on the forward partial and on the reverse sweep, ...). The stages
+// of one level that share a task type (k-loop tile or strip of one variant,
+// gram tile, streaming gram, reduce) form a group; each group is one
+// persistent launch whose workgroups stride over its tasks with a kernel
+// compiled for that task type alone (so its registers and LDS are sized for
+// it). Groups are launched level by level on one stream, so kernel
+// boundaries order the dependencies and no workgroup ever waits for another.
+// Capturing kp_tucker_batched in a HIP graph turns the whole batch into one
+// graph.
 #include "kp.h"
 
 #include <string.h>
 
 #include <algorithm>
+#include <array>
+#include <mutex>
+#include <unordered_map>
+#include <utility>
 #include <vector>
 
+#include "gram_strip.h"
 #include "gram_tile.h"
 #include "kp_common.h"
 #include "kp_internal.h"
 #include "mode_tile.h"
+#include "strip_tile.h"
 
 namespace kp {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr uint64_t kMagic = 0x6b70626174636802ULL;  // "kpbatch" v2
+constexpr uint64_t kMagic = 0x6b70626174636803ULL;  // "kpbatch" v3
 constexpr int kGramBR = 32;
+constexpr int64_t kStripTiles = 16;   // fiber tiles per strip task
+constexpr int64_t kGramChunks = 8;    // fiber chunks per streaming gram task
 
-enum StageKind { ST_MODE = 0, ST_GRAM = 1, ST_REDUCE = 2 };
+// ST_MODE: k-loop tiles; ST_STRIP: strip tasks (a run of fiber tiles of one
+// n block, strip_tile.h); ST_GRAM: 64 x 64 gram tiles of one split;
+// ST_GSTRIP: one streaming gram partial (gram_strip.h); ST_REDUCE: 16
+// outputs of the fixed-order sum of a gram's partial tiles.
+enum StageKind { ST_MODE = 0, ST_GRAM = 1, ST_REDUCE = 2, ST_STRIP = 3, ST_GSTRIP = 4 };
 
 struct BStage {
   int32_t kind;
@@ -42,20 +56,21 @@ struct BStage {
   int64_t begin;          // first global task number of this stage
   ModeArgs m;             // ST_MODE
   gram::GramArgs g;       // ST_GRAM (and n, m, part for ST_REDUCE)
-  int64_t splits;         // ST_REDUCE
+  int64_t splits;         // ST_REDUCE, ST_GSTRIP: number of partial tiles
   void* dL;               // ST_REDUCE output
   int64_t rs, cs;
+  int64_t ntiles;         // ST_STRIP: fiber tiles; ST_GSTRIP: fiber chunks
 };
 
 // Plan layout: [BHeader][BStage x nstages][int64 level_begin x (nlevels + 1)]
-// level_begin[l] is the first task number of level l.
+// [BGroup x ngroups]; level_begin[l] is the first task number of level l.
 struct BHeader {
   uint64_t magic;
   int32_t nstages;
   int32_t form;
   int64_t ntasks;
   int32_t nlevels;
-  int32_t pad_;
+  int32_t ngroups;
   const void* ws_base;
   size_t ws_bytes;
 };
@@ -92,6 +107,52 @@ struct BVars<FORM_BF16X6> {
   static constexpr int n = 4;
 };
 
+// Strip variants of the executor, per form: (nb, fb, kp); fb per kp as in
+// the standalone strip kernels.
+struct SVar {
+  int nb, fb, kp;
+};
+constexpr SVar kSVarF32[] = {{1, 2, 16}, {2, 2, 16}, {4, 2, 16}, {1, 2, 32}, {2, 2, 32},
+                             {4, 2, 32}, {1, 1, 64}, {2, 1, 64}, {4, 1, 64}};
+constexpr SVar kSVarF64[] = {{2, 2, 16}, {4, 2, 16}, {2, 1, 32}, {4, 1, 32}};
+constexpr SVar kSVarB3[] = {{2, 2, 32}, {4, 2, 32}, {2, 1, 64}, {4, 1, 64}};
+constexpr SVar kSVarB6[] = {{2, 1, 32}, {4, 1, 32}, {2, 1, 64}, {4, 1, 64}};
+
+template <int FORM>
+struct SVars;
+template <>
+struct SVars<FORM_F32> {
+  static constexpr const SVar* v = kSVarF32;
+  static constexpr int n = 9;
+};
+template <>
+struct SVars<FORM_F64> {
+  static constexpr const SVar* v = kSVarF64;
+  static constexpr int n = 4;
+};
+template <>
+struct SVars<FORM_BF16X3> {
+  static constexpr const SVar* v = kSVarB3;
+  static constexpr int n = 4;
+};
+template <>
+struct SVars<FORM_BF16X6> {
+  static constexpr const SVar* v = kSVarB6;
+  static constexpr int n = 4;
+};
+
+const SVar* host_svars(int form, int* count) {
+  switch (form) {
+    case FORM_F32: *count = 9; return kSVarF32;
+    case FORM_F64: *count = 4; return kSVarF64;
+    case FORM_BF16X3: *count = 4; return kSVarB3;
+    default: *count = 4; return kSVarB6;
+  }
+}
+
+template <typename E>
+constexpr int gstrip_br() { return sizeof(E) == 8 ? 32 : 64; }
+
 const BVar* host_vars(int form, int* count) {
   switch (form) {
     case FORM_F64: *count = 5; return kBVarF64;
@@ -100,55 +161,72 @@ const BVar* host_vars(int form, int* count) {
   }
 }
 
-template <int FORM, int I>
-constexpr size_t max_mode_lds() {
-  if constexpr (I == BVars<FORM>::n) {
-    return 0;
+// LDS of one (kind, variant) task type.
+template <int FORM, int KIND, int VAR>
+constexpr size_t task_lds() {
+  using E = typename tile::FormT<FORM>::G;
+  if constexpr (KIND == ST_MODE) {
+    constexpr BVar v = BVars<FORM>::v[VAR / 2];
+    return tile::mode_lds_bytes<FORM, v.nb, v.fb, v.bk>();
+  } else if constexpr (KIND == ST_STRIP) {
+    constexpr SVar v = SVars<FORM>::v[VAR / 2];
+    return tile::strip_lds_bytes<FORM, v.nb, v.fb, v.kp>();
+  } else if constexpr (KIND == ST_GRAM) {
+    return gram::gram_lds_bytes<E, kGramBR>();
+  } else if constexpr (KIND == ST_GSTRIP) {
+    return gram::strip_lds_bytes<E, (VAR & 4) ? 4 : 2, (VAR & 2) ? 4 : 2, gstrip_br<E>()>();
   } else {
-    constexpr BVar b = BVars<FORM>::v[I];
-    constexpr size_t here = tile::mode_lds_bytes<FORM, b.nb, b.fb, b.bk>();
-    constexpr size_t rest = max_mode_lds<FORM, I + 1>();
-    return here > rest ? here : rest;
+    return kThreads * sizeof(E);
   }
 }
 
-template <int FORM>
-constexpr size_t batch_lds() {
+// One task of a stage; the task type is fixed at compile time.
+template <int FORM, int KIND, int VAR>
+__device__ __forceinline__ void run_task(const BStage& S, int64_t tile_id, char* lds) {
   using E = typename tile::FormT<FORM>::G;
-  constexpr size_t a = max_mode_lds<FORM, 0>();
-  constexpr size_t b = gram::gram_lds_bytes<E, kGramBR>();
-  return a > b ? a : b;
-}
-
-// Variant id = 2 * index + inner.
-template <int FORM, int I>
-__device__ __forceinline__ void run_mode_variant(int id, const ModeArgs& a, int64_t bx,
-                                                 int64_t by, char* lds) {
-  if constexpr (I < BVars<FORM>::n) {
-    constexpr BVar b = BVars<FORM>::v[I];
-    if (id == 2 * I) {
-      tile::mode_tile<FORM, b.nb, b.fb, b.bk, false>(a, bx, by, lds);
-    } else if (id == 2 * I + 1) {
-      tile::mode_tile<FORM, b.nb, b.fb, b.bk, true>(a, bx, by, lds);
-    } else {
-      run_mode_variant<FORM, I + 1>(id, a, bx, by, lds);
-    }
+  constexpr bool INNER = (VAR & 1) != 0;
+  if constexpr (KIND == ST_MODE) {
+    constexpr BVar v = BVars<FORM>::v[VAR / 2];
+    const int64_t bx = tile_id % S.tx;
+    const int64_t by = tile_id / S.tx;
+    tile::mode_tile<FORM, v.nb, v.fb, v.bk, INNER>(S.m, bx, by, lds);
+  } else if constexpr (KIND == ST_STRIP) {
+    constexpr SVar v = SVars<FORM>::v[VAR / 2];
+    const int64_t sx = tile_id % S.tx;
+    const int64_t by = tile_id / S.tx;
+    const int64_t t0 = sx * S.ntiles / S.tx, t1 = (sx + 1) * S.ntiles / S.tx;
+    tile::strip_run<FORM, v.nb, v.fb, v.kp, INNER, false>(S.m, by, t0, 1, t1, lds);
+  } else if constexpr (KIND == ST_GRAM) {
+    const int64_t bx = tile_id % S.tx;
+    const int64_t by = (tile_id / S.tx) % S.ty;
+    const int64_t bz = tile_id / (static_cast<int64_t>(S.tx) * S.ty);
+    gram::gram_tile<E, kGramBR, INNER>(S.g, bx, by, bz, lds);
+  } else if constexpr (KIND == ST_GSTRIP) {
+    const int64_t cb = tile_id * S.ntiles / S.splits;
+    const int64_t ce = (tile_id + 1) * S.ntiles / S.splits;
+    gram::gram_strip<E, (VAR & 4) ? 4 : 2, (VAR & 2) ? 4 : 2, gstrip_br<E>(), INNER>(
+        S.g, cb, ce, static_cast<E*>(S.g.part) + tile_id * S.g.n * S.g.m, lds);
+  } else {
+    gram::gram_reduce_block<E>(static_cast<const E*>(S.g.part), S.splits, S.g.n, S.g.m,
+                               static_cast<E*>(S.dL), S.rs, S.cs, tile_id,
+                               reinterpret_cast<E*>(lds));
   }
 }
 
-// Runs the tiles [task_begin, task_end) of one level; workgroup b takes tasks
-// task_begin + b, task_begin + b + gridDim.x, ... No task of a level depends
-// on another task of the same level.
-template <int FORM>
-__global__ __launch_bounds__(kThreads) void batch_level_kernel(const BStage* __restrict__ st,
-                                                               int nstages, int64_t task_begin,
-                                                               int64_t task_end) {
-  using E = typename tile::FormT<FORM>::G;
-  __shared__ __attribute__((aligned(16))) char lds[batch_lds<FORM>()];
-  const int t = threadIdx.x;
+// Runs the tasks [task_begin, task_end) of one group: the stages
+// [s_begin, s_end) of one level that share a task type. Workgroup b takes
+// tasks task_begin + b, task_begin + b + gridDim.x, ...; no task of a level
+// depends on another task of the same level.
+template <int FORM, int KIND, int VAR>
+__global__ __launch_bounds__(kThreads, 2) void batch_group_kernel(const BStage* __restrict__ st,
+                                                                  int s_begin, int s_end,
+                                                                  int64_t task_begin,
+                                                                  int64_t task_end) {
+  __shared__ __attribute__((aligned(16))) char lds[task_lds<FORM, KIND, VAR>()];
   for (int64_t task = task_begin + blockIdx.x; task < task_end; task += gridDim.x) {
-    // stage of this task: the last stage whose begin <= task
-    int lo = 0, hi = nstages - 1;
+    // stage of this task: the last stage whose begin <= task (the same in
+    // every lane, so its fields are read with scalar loads)
+    int lo = s_begin, hi = s_end - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
       if (st[mid].begin <= task)
@@ -156,32 +234,47 @@ __global__ __launch_bounds__(kThreads) void batch_level_kernel(const BStage* __r
       else
         hi = mid - 1;
     }
+    lo = __builtin_amdgcn_readfirstlane(lo);
     const BStage& S = st[lo];
-    const int64_t tile_id = task - S.begin;
-    __syncthreads();  // the previous tile's LDS reads are complete
-    if (S.kind == ST_MODE) {
-      const int64_t bx = tile_id % S.tx;
-      const int64_t by = tile_id / S.tx;
-      run_mode_variant<FORM, 0>(S.variant, S.m, bx, by, lds);
-    } else if (S.kind == ST_GRAM) {
-      const int64_t bx = tile_id % S.tx;
-      const int64_t by = (tile_id / S.tx) % S.ty;
-      const int64_t bz = tile_id / (static_cast<int64_t>(S.tx) * S.ty);
-      if (S.variant)
-        gram::gram_tile<E, kGramBR, true>(S.g, bx, by, bz, lds);
-      else
-        gram::gram_tile<E, kGramBR, false>(S.g, bx, by, bz, lds);
-    } else {
-      const int64_t nm = S.g.n * S.g.m;
-      const int64_t idx = tile_id * kThreads + t;
-      if (idx < nm) {
-        const E* part = static_cast<const E*>(S.g.part);
-        E s = E(0);
-        for (int64_t k = 0; k < S.splits; ++k) s += part[k * nm + idx];
-        const int64_t i = idx / S.g.m, j = idx - (idx / S.g.m) * S.g.m;
-        static_cast<E*>(S.dL)[i * S.rs + j * S.cs] = s;
-      }
+    __syncthreads();  // the previous task's LDS reads are complete
+    run_task<FORM, KIND, VAR>(S, task - S.begin, lds);
+  }
+}
+
+using GroupFn = void (*)(const BStage*, int, int, int64_t, int64_t);
+
+// Kernel table of a form: index = kind-specific offset + variant.
+template <int FORM, int KIND, int... V>
+constexpr std::array<GroupFn, sizeof...(V)> group_fns(std::integer_sequence<int, V...>) {
+  return {{batch_group_kernel<FORM, KIND, V>...}};
+}
+
+template <int FORM>
+struct GroupTable {
+  static constexpr int NM = 2 * BVars<FORM>::n, NS = 2 * SVars<FORM>::n;
+  static constexpr auto mode = group_fns<FORM, ST_MODE>(std::make_integer_sequence<int, NM>{});
+  static constexpr auto strip = group_fns<FORM, ST_STRIP>(std::make_integer_sequence<int, NS>{});
+  static constexpr auto gram = group_fns<FORM, ST_GRAM>(std::make_integer_sequence<int, 2>{});
+  static constexpr auto gstrip = group_fns<FORM, ST_GSTRIP>(std::make_integer_sequence<int, 8>{});
+  static constexpr auto reduce = group_fns<FORM, ST_REDUCE>(std::make_integer_sequence<int, 1>{});
+  static GroupFn get(int kind, int var) {
+    switch (kind) {
+      case ST_MODE: return var >= 0 && var < NM ? mode[var] : nullptr;
+      case ST_STRIP: return var >= 0 && var < NS ? strip[var] : nullptr;
+      case ST_GRAM: return var >= 0 && var < 2 ? gram[var] : nullptr;
+      case ST_GSTRIP: return var >= 0 && var < 8 ? gstrip[var] : nullptr;
+      case ST_REDUCE: return var == 0 ? reduce[0] : nullptr;
+      default: return nullptr;
     }
+  }
+};
+
+GroupFn group_fn(int form, int kind, int var) {
+  switch (form) {
+    case FORM_F64: return GroupTable<FORM_F64>::get(kind, var);
+    case FORM_F32: return GroupTable<FORM_F32>::get(kind, var);
+    case FORM_BF16X3: return GroupTable<FORM_BF16X3>::get(kind, var);
+    default: return GroupTable<FORM_BF16X6>::get(kind, var);
   }
 }
 
@@ -195,10 +288,18 @@ int64_t numel_t(const kp_tensor& t) {
   return s;
 }
 
+// One launch: stages [s_begin, s_end) of one level and one task type,
+// tasks [t_begin, t_end).
+struct BGroup {
+  int32_t kind, variant, s_begin, s_end, level, pad_;
+  int64_t t_begin, t_end;
+};
+
 struct Plan {
   std::vector<BStage> stages;
   std::vector<int> level;
   std::vector<int64_t> level_begin;  // after finalize
+  std::vector<BGroup> groups;        // after finalize
   size_t ws_total = 0;
 };
 
@@ -226,6 +327,56 @@ int pick_batch_variant(int form, const ModeArgs& a) {
     }
   }
   return 2 * best + (a.Il > 1 ? 1 : 0);
+}
+
+// Strip variant of the executor for a product whose tuned / default tile is
+// a strip: the same (nb, kp) if the executor has it, else the shortest strip
+// covering m with the least n padding; -1 if no strip covers m.
+int pick_strip_variant(int form, const ModeArgs& a, const ModeTile& want) {
+  int nv;
+  const SVar* vs = host_svars(form, &nv);
+  int best = -1;
+  int64_t best_cost = 0;
+  for (int i = 0; i < nv; ++i) {
+    if (vs[i].kp < a.m) continue;
+    if (vs[i].nb == want.nb && vs[i].kp == want.bk) return i;
+    const int64_t bn = 16 * vs[i].nb;
+    const int64_t padded = ((a.n + bn - 1) / bn) * bn;
+    const int64_t cost = static_cast<int64_t>(vs[i].kp) * 4096 + (padded - a.n);
+    if (best < 0 || cost < best_cost) {
+      best = i;
+      best_cost = cost;
+    }
+  }
+  return best;
+}
+
+// Kind, variant and task grid of a mode-product stage (b.m set).
+void set_mode_stage(int form, BStage& b) {
+  const ModeTile want = default_mode_tile(form, b.m);
+  const bool inner = b.m.Il > 1;
+  const int64_t F = inner ? b.m.Il * b.m.Ir : b.m.Ir;
+  if (want.kind == 1) {
+    const int sv = pick_strip_variant(form, b.m, want);
+    if (sv >= 0) {
+      int nv;
+      const SVar& v = host_svars(form, &nv)[sv];
+      b.kind = ST_STRIP;
+      b.variant = 2 * sv + (inner ? 1 : 0);
+      b.ntiles = (F + 64 * v.fb - 1) / (64 * v.fb);
+      b.tx = static_cast<int32_t>((b.ntiles + kStripTiles - 1) / kStripTiles);
+      b.ty = static_cast<int32_t>((b.m.n + 16 * v.nb - 1) / (16 * v.nb));
+      b.tz = 1;
+      return;
+    }
+  }
+  b.kind = ST_MODE;
+  b.variant = pick_batch_variant(form, b.m);
+  int nv;
+  const BVar& bv = host_vars(form, &nv)[b.variant / 2];
+  b.tx = static_cast<int32_t>((F + 64 * bv.fb - 1) / (64 * bv.fb));
+  b.ty = static_cast<int32_t>((b.m.n + 16 * bv.nb - 1) / (16 * bv.nb));
+  b.tz = 1;
 }
 
 size_t aligned(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
@@ -338,16 +489,8 @@ int build_plan(int count, const kp_batch_item* items, int prec, char* ws_base, P
         Y = region(static_cast<size_t>(e) * es);
       }
       BStage b{};
-      b.kind = ST_MODE;
       b.m = mode_args(P[s - 1], Y, dims[s - 1], d, s - 1, L, 0);
-      b.variant = pick_batch_variant(form, b.m);
-      int nv;
-      const BVar* vs = host_vars(form, &nv);
-      const BVar& bv = vs[b.variant / 2];
-      const int64_t F = b.m.Il > 1 ? b.m.Il * b.m.Ir : b.m.Ir;
-      b.tx = static_cast<int32_t>((F + 64 * bv.fb - 1) / (64 * bv.fb));
-      b.ty = static_cast<int32_t>((b.m.n + 16 * bv.nb - 1) / (16 * bv.nb));
-      b.tz = 1;
+      set_mode_stage(form, b);
       b.dep0 = fstage[s - 1];
       b.dep1 = -1;
       b.problem = q;
@@ -380,18 +523,35 @@ int build_plan(int count, const kp_batch_item* items, int prec, char* ws_base, P
         g.n = L.rows;
         g.m = L.cols;
         g.Ir = Ir;
-        g.achunks = inner ? (Il + kGramBR - 1) / kGramBR : 1;
-        g.chunks = inner ? Ir * g.achunks : (Ir + kGramBR - 1) / kGramBR;
-        const int64_t splits = batch_gram_splits(g.chunks);
-        g.per_split = (g.chunks + splits - 1) / splits;
-        g.part = region(static_cast<size_t>(splits * g.n * g.m) * es);
         BStage b{};
-        b.kind = ST_GRAM;
-        b.variant = inner ? 1 : 0;
+        int64_t splits;
+        if (g.n <= 64 && g.m <= 64) {
+          // streaming partials: each task a contiguous run of fiber chunks
+          const int64_t br = es == 8 ? 32 : 64;
+          const int64_t chunks = (Il * Ir + br - 1) / br;
+          splits = (chunks + kGramChunks - 1) / kGramChunks;
+          if (splits > 1024) splits = 1024;
+          if (splits < 1) splits = 1;
+          g.part = region(static_cast<size_t>(splits * g.n * g.m) * es);
+          b.kind = ST_GSTRIP;
+          b.variant = (inner ? 1 : 0) + (g.m > 32 ? 2 : 0) + (g.n > 32 ? 4 : 0);
+          b.ntiles = chunks;
+          b.splits = splits;
+          b.tx = static_cast<int32_t>(splits);
+          b.ty = b.tz = 1;
+        } else {
+          g.achunks = inner ? (Il + kGramBR - 1) / kGramBR : 1;
+          g.chunks = inner ? Ir * g.achunks : (Ir + kGramBR - 1) / kGramBR;
+          splits = batch_gram_splits(g.chunks);
+          g.per_split = (g.chunks + splits - 1) / splits;
+          g.part = region(static_cast<size_t>(splits * g.n * g.m) * es);
+          b.kind = ST_GRAM;
+          b.variant = inner ? 1 : 0;
+          b.tx = static_cast<int32_t>((g.n + 63) / 64);
+          b.ty = static_cast<int32_t>((g.m + 63) / 64);
+          b.tz = static_cast<int32_t>(splits);
+        }
         b.g = g;
-        b.tx = static_cast<int32_t>((g.n + 63) / 64);
-        b.ty = static_cast<int32_t>((g.m + 63) / 64);
-        b.tz = static_cast<int32_t>(splits);
         b.dep0 = qstage;
         b.dep1 = fstage[k];
         b.problem = q;
@@ -404,7 +564,7 @@ int build_plan(int count, const kp_batch_item* items, int prec, char* ws_base, P
         r.dL = it.dL[k].data;
         r.rs = it.dL[k].rs;
         r.cs = it.dL[k].cs;
-        r.tx = static_cast<int32_t>((g.n * g.m + kThreads - 1) / kThreads);
+        r.tx = static_cast<int32_t>((g.n * g.m + 15) / 16);
         r.ty = r.tz = 1;
         r.dep0 = gs;
         r.dep1 = -1;
@@ -426,16 +586,8 @@ int build_plan(int count, const kp_batch_item* items, int prec, char* ws_base, P
           Y = region(static_cast<size_t>(e) * es);
         }
         BStage b{};
-        b.kind = ST_MODE;
         b.m = mode_args(Qmu, Y, qd, d, k, Lt, 0);
-        b.variant = pick_batch_variant(form, b.m);
-        int nv;
-        const BVar* vs = host_vars(form, &nv);
-        const BVar& bv = vs[b.variant / 2];
-        const int64_t F = b.m.Il > 1 ? b.m.Il * b.m.Ir : b.m.Ir;
-        b.tx = static_cast<int32_t>((F + 64 * bv.fb - 1) / (64 * bv.fb));
-        b.ty = static_cast<int32_t>((b.m.n + 16 * bv.nb - 1) / (16 * bv.nb));
-        b.tz = 1;
+        set_mode_stage(form, b);
         b.dep0 = qstage;
         b.dep1 = -1;
         b.problem = q;
@@ -450,21 +602,27 @@ int build_plan(int count, const kp_batch_item* items, int prec, char* ws_base, P
   return form;
 }
 
-// Orders stages by (level, problem) keeping dependencies earlier, rewrites
-// the dependency indices and numbers the tasks.
+// Orders stages by (level, task type, problem) keeping dependencies
+// earlier, rewrites the dependency indices, numbers the tasks and forms the
+// launch groups: runs of stages of one level with one task type.
 int64_t finalize(Plan* pl) {
   const int n = static_cast<int>(pl->stages.size());
   std::vector<int> idx(n);
   for (int i = 0; i < n; ++i) idx[i] = i;
   std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
+    const BStage& x = pl->stages[a];
+    const BStage& y = pl->stages[b];
     if (pl->level[a] != pl->level[b]) return pl->level[a] < pl->level[b];
-    return pl->stages[a].problem < pl->stages[b].problem;
+    if (x.kind != y.kind) return x.kind < y.kind;
+    if (x.variant != y.variant) return x.variant < y.variant;
+    return x.problem < y.problem;
   });
   std::vector<int> pos(n);
   for (int i = 0; i < n; ++i) pos[idx[i]] = i;
   std::vector<BStage> out(n);
   int64_t task = 0;
   pl->level_begin.clear();
+  pl->groups.clear();
   int cur_level = -1;
   for (int i = 0; i < n; ++i) {
     BStage s = pl->stages[idx[i]];
@@ -476,7 +634,21 @@ int64_t finalize(Plan* pl) {
     if (s.dep0 >= 0) s.dep0 = pos[s.dep0];
     if (s.dep1 >= 0) s.dep1 = pos[s.dep1];
     s.begin = task;
-    task += static_cast<int64_t>(s.tx) * s.ty * s.tz;
+    const int64_t nt = static_cast<int64_t>(s.tx) * s.ty * s.tz;
+    BGroup* g = pl->groups.empty() ? nullptr : &pl->groups.back();
+    if (!g || g->level != lv || g->kind != s.kind || g->variant != s.variant) {
+      BGroup ng{};
+      ng.kind = s.kind;
+      ng.variant = s.variant;
+      ng.s_begin = i;
+      ng.level = lv;
+      ng.t_begin = task;
+      pl->groups.push_back(ng);
+      g = &pl->groups.back();
+    }
+    g->s_end = i + 1;
+    g->t_end = task + nt;
+    task += nt;
     out[i] = s;
   }
   pl->level_begin.push_back(task);
@@ -484,41 +656,43 @@ int64_t finalize(Plan* pl) {
   return task;
 }
 
-// Persistent workgroups for a form: all that fit on the device at once.
-template <int FORM>
-int batch_blocks() {
-  static int blocks = 0;
-  if (blocks == 0) {
-    int dev = 0, cus = 0, per = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        cus <= 0)
-      cus = 256;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batch_level_kernel<FORM>, kThreads,
-                                                     0) !=
-            hipSuccess ||
-        per <= 0)
-      per = 1;
-    blocks = cus * per;
-  }
-  return blocks;
+// Resident workgroups of a kernel on the device (queried once per kernel).
+int group_blocks(GroupFn fn) {
+  static std::mutex mu;
+  static std::unordered_map<const void*, int> cache;
+  std::lock_guard<std::mutex> lock(mu);
+  const auto it = cache.find(reinterpret_cast<const void*>(fn));
+  if (it != cache.end()) return it->second;
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus <= 0)
+    cus = 256;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(fn),
+                                                   kThreads, 0) != hipSuccess ||
+      per <= 0)
+    per = 1;
+  cache[reinterpret_cast<const void*>(fn)] = cus * per;
+  return cus * per;
 }
 
 }  // namespace
 
 int list_batch_variants(int form, int32_t* out, int cap) {
-  int nv;
+  int nv, ns;
   const BVar* vs = host_vars(form, &nv);
-  for (int i = 0; i < nv && i < cap; ++i) {
+  const SVar* ss = host_svars(form, &ns);
+  for (int i = 0; i < nv + ns && i < cap; ++i) {
     int32_t* o = out + 6 * i;
-    o[0] = vs[i].nb;
-    o[1] = vs[i].fb;
-    o[2] = vs[i].bk;
+    const bool strip = i >= nv;
+    o[0] = strip ? ss[i - nv].nb : vs[i].nb;
+    o[1] = strip ? ss[i - nv].fb : vs[i].fb;
+    o[2] = strip ? ss[i - nv].kp : vs[i].bk;
     o[3] = 0;
     o[4] = 0;
-    o[5] = 0;
+    o[5] = strip ? 1 : 0;
   }
-  return nv;
+  return nv + ns;
 }
 
 }  // namespace kp
@@ -538,7 +712,7 @@ size_t kp_batch_plan_bytes(int count, const kp_batch_item* items, int prec) {
   if (build_plan(count, items, prec, nullptr, &pl) < 0) return 0;
   finalize(&pl);
   return sizeof(BHeader) + pl.stages.size() * sizeof(BStage) +
-         pl.level_begin.size() * sizeof(int64_t);
+         pl.level_begin.size() * sizeof(int64_t) + pl.groups.size() * sizeof(BGroup);
 }
 
 int kp_batch_plan(int count, const kp_batch_item* items, int prec, void* ws, size_t ws_bytes,
@@ -550,7 +724,7 @@ int kp_batch_plan(int count, const kp_batch_item* items, int prec, void* ws, siz
   if (ws_bytes < pl.ws_total) return KP_ERR_WORKSPACE;
   const int64_t ntasks = finalize(&pl);
   const size_t need = sizeof(BHeader) + pl.stages.size() * sizeof(BStage) +
-                      pl.level_begin.size() * sizeof(int64_t);
+                      pl.level_begin.size() * sizeof(int64_t) + pl.groups.size() * sizeof(BGroup);
   if (plan_bytes < need) return KP_ERR_WORKSPACE;
   BHeader h{};
   h.magic = kMagic;
@@ -558,6 +732,7 @@ int kp_batch_plan(int count, const kp_batch_item* items, int prec, void* ws, siz
   h.form = form;
   h.ntasks = ntasks;
   h.nlevels = static_cast<int32_t>(pl.level_begin.size()) - 1;
+  h.ngroups = static_cast<int32_t>(pl.groups.size());
   h.ws_base = ws;
   h.ws_bytes = ws_bytes;
   char* p = static_cast<char*>(plan);
@@ -566,6 +741,8 @@ int kp_batch_plan(int count, const kp_batch_item* items, int prec, void* ws, siz
   if (!pl.stages.empty()) memcpy(p, pl.stages.data(), pl.stages.size() * sizeof(BStage));
   p += pl.stages.size() * sizeof(BStage);
   memcpy(p, pl.level_begin.data(), pl.level_begin.size() * sizeof(int64_t));
+  p += pl.level_begin.size() * sizeof(int64_t);
+  if (!pl.groups.empty()) memcpy(p, pl.groups.data(), pl.groups.size() * sizeof(BGroup));
   return KP_OK;
 }
 
@@ -590,37 +767,22 @@ int kp_tucker_batched(const void* plan_dev, const void* plan, void* ws, size_t w
   if (h.nstages == 0) return KP_OK;
   const BStage* sd = reinterpret_cast<const BStage*>(static_cast<const char*>(plan_dev) +
                                                      sizeof(BHeader));
-  const int64_t* lb = reinterpret_cast<const int64_t*>(
-      static_cast<const char*>(plan) + sizeof(BHeader) + h.nstages * sizeof(BStage));
-  int blocks;
-  switch (h.form) {
-    case FORM_F64: blocks = batch_blocks<FORM_F64>(); break;
-    case FORM_F32: blocks = batch_blocks<FORM_F32>(); break;
-    case FORM_BF16X3: blocks = batch_blocks<FORM_BF16X3>(); break;
-    default: blocks = batch_blocks<FORM_BF16X6>(); break;
-  }
-  for (int l = 0; l < h.nlevels; ++l) {
-    const int64_t b = lb[l], e = lb[l + 1];
-    if (e <= b) continue;
-    const unsigned grid = static_cast<unsigned>(e - b < blocks ? e - b : blocks);
-    switch (h.form) {
-      case FORM_F64:
-        hipLaunchKernelGGL(batch_level_kernel<FORM_F64>, dim3(grid), dim3(kThreads), 0, stream,
-                           sd, h.nstages, b, e);
-        break;
-      case FORM_F32:
-        hipLaunchKernelGGL(batch_level_kernel<FORM_F32>, dim3(grid), dim3(kThreads), 0, stream,
-                           sd, h.nstages, b, e);
-        break;
-      case FORM_BF16X3:
-        hipLaunchKernelGGL(batch_level_kernel<FORM_BF16X3>, dim3(grid), dim3(kThreads), 0,
-                           stream, sd, h.nstages, b, e);
-        break;
-      default:
-        hipLaunchKernelGGL(batch_level_kernel<FORM_BF16X6>, dim3(grid), dim3(kThreads), 0,
-                           stream, sd, h.nstages, b, e);
-        break;
-    }
+  const BGroup* gr = reinterpret_cast<const BGroup*>(
+      static_cast<const char*>(plan) + sizeof(BHeader) + h.nstages * sizeof(BStage) +
+      (h.nlevels + 1) * sizeof(int64_t));
+  // one launch per group, in plan order (levels ascending): kernel
+  // boundaries on the stream order the levels
+  for (int q = 0; q < h.ngroups; ++q) {
+    const BGroup& g = gr[q];
+    if (g.s_begin < 0 || g.s_end > h.nstages || g.s_begin >= g.s_end) return KP_ERR_VALUE;
+    if (g.t_end <= g.t_begin) continue;
+    const GroupFn fn = group_fn(h.form, g.kind, g.variant);
+    if (!fn) return KP_ERR_VALUE;
+    const int64_t blocks = group_blocks(fn);
+    const int64_t tasks = g.t_end - g.t_begin;
+    const unsigned grid = static_cast<unsigned>(tasks < blocks ? tasks : blocks);
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(kThreads), 0, stream, sd, g.s_begin, g.s_end,
+                       g.t_begin, g.t_end);
     const hipError_t err = hipGetLastError();
     if (err != hipSuccess) return hip_status(err);
   }

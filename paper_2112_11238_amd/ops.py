@@ -254,7 +254,8 @@ def expm(A, tau=1.0):
 
 class BatchedTucker:
     """Many independent Tucker operators (and optionally their gradients):
-    one persistent launch per dependency level (kp_tucker_batched).
+    one persistent launch per dependency level and task type
+    (kp_tucker_batched).
 
     Ts[k] is a tensor of order d_k, Ls[k] its d_k factors (no None); all share
     a dtype. With ``Gs`` (cotangents, shapes of the outputs) the backward runs

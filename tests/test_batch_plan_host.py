@@ -31,13 +31,21 @@ class StageC(ctypes.Structure):
                 ("ty", ctypes.c_int32), ("tz", ctypes.c_int32), ("dep0", ctypes.c_int32),
                 ("dep1", ctypes.c_int32), ("problem", ctypes.c_int32), ("begin", ctypes.c_int64),
                 ("m", ModeArgsC), ("g", GramArgsC), ("splits", ctypes.c_int64),
-                ("dL", ctypes.c_uint64), ("rs", ctypes.c_int64), ("cs", ctypes.c_int64)]
+                ("dL", ctypes.c_uint64), ("rs", ctypes.c_int64), ("cs", ctypes.c_int64),
+                ("ntiles", ctypes.c_int64)]
+
+
+class GroupC(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("variant", ctypes.c_int32),
+                ("s_begin", ctypes.c_int32), ("s_end", ctypes.c_int32),
+                ("level", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("t_begin", ctypes.c_int64), ("t_end", ctypes.c_int64)]
 
 
 class HeaderC(ctypes.Structure):
     _fields_ = [("magic", ctypes.c_uint64), ("nstages", ctypes.c_int32),
                 ("form", ctypes.c_int32), ("ntasks", ctypes.c_int64),
-                ("nlevels", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("nlevels", ctypes.c_int32), ("ngroups", ctypes.c_int32),
                 ("ws_base", ctypes.c_uint64), ("ws_bytes", ctypes.c_uint64)]
 
 
@@ -98,6 +106,10 @@ def plan(lib, L, items, count, prec):
     st = (StageC * h.nstages).from_buffer_copy(raw[o:o + h.nstages * ctypes.sizeof(StageC)])
     o += h.nstages * ctypes.sizeof(StageC)
     lb = list((ctypes.c_int64 * (h.nlevels + 1)).from_buffer_copy(raw[o:o + 8 * (h.nlevels + 1)]))
+    o += 8 * (h.nlevels + 1)
+    gr = list((GroupC * h.ngroups).from_buffer_copy(raw[o:o + h.ngroups * ctypes.sizeof(GroupC)]))
+    assert o + h.ngroups * ctypes.sizeof(GroupC) == len(raw)
+    plan.groups = gr
     return h, list(st), ws_bytes, lb
 
 
@@ -142,12 +154,25 @@ def test_plan_is_ordered_and_in_bounds(lib, L, dtype, prec, backward):
         for dep in (s.dep0, s.dep1):
             if dep >= 0:
                 assert dep < i and level_of(dep) < level_of(i)
+    # launch groups: consecutive, covering every stage and task once, one
+    # task type and one level each, levels ascending
+    gr = plan.groups
+    assert gr[0].s_begin == 0 and gr[-1].s_end == len(st)
+    assert gr[0].t_begin == 0 and gr[-1].t_end == h.ntasks
+    for a, b in zip(gr, gr[1:]):
+        assert a.s_end == b.s_begin and a.t_end == b.t_begin and a.level <= b.level
+    for g in gr:
+        assert g.s_begin < g.s_end
+        assert g.t_begin == st[g.s_begin].begin
+        for i in range(g.s_begin, g.s_end):
+            assert (st[i].kind, st[i].variant) == (g.kind, g.variant)
+            assert level_of(i) == g.level
     ws = (FAKE_WS, ws_bytes)
     user = list(alloc.ranges.values())
     # every access inside the user buffers or the workspace; outputs distinct
     writes = []
     for s in st:
-        if s.kind == 0:
+        if s.kind in (0, 3):
             mm = s.m
             F = mm.Il * mm.Ir
             assert within(mm.X, F * mm.m * es, user + [ws])
@@ -155,6 +180,17 @@ def test_plan_is_ordered_and_in_bounds(lib, L, dtype, prec, backward):
             span = ((mm.n - 1) * mm.rs + (mm.m - 1) * mm.cs + 1) * es
             assert within(mm.L, span, user)
             writes.append((mm.Y, F * mm.n * es))
+            if s.kind == 3:       # strip: every fiber tile of every n block once
+                assert s.ntiles >= 1 and 1 <= s.tx <= s.ntiles
+        elif s.kind == 4:
+            g = s.g
+            F = g.Il * g.Ir
+            assert within(g.Q, F * g.n * es, user + [ws])
+            assert within(g.P, F * g.m * es, user + [ws])
+            assert s.tx == s.splits and s.ty == s.tz == 1 and 1 <= s.splits <= s.ntiles
+            assert g.n <= 64 and g.m <= 64
+            assert within(g.part, s.splits * g.n * g.m * es, [ws])
+            writes.append((g.part, s.splits * g.n * g.m * es))
         elif s.kind == 1:
             g = s.g
             F = g.Il * g.Ir
@@ -164,6 +200,8 @@ def test_plan_is_ordered_and_in_bounds(lib, L, dtype, prec, backward):
             assert g.chunks <= s.tz * g.per_split
             writes.append((g.part, s.tz * g.n * g.m * es))
         else:
+            assert s.kind == 2
+            assert s.tx == (s.g.n * s.g.m + 15) // 16
             assert within(s.dL, s.g.n * s.g.m * es, user)
             writes.append((s.dL, s.g.n * s.g.m * es))
     writes.sort()

@@ -50,8 +50,8 @@ def test_variant_lists(lib, tune):
         # every tile of the batched executor has a standalone kernel with the
         # same (nb, fb, bk): the throughput tuner times it there
         for v in tune.variants(form, batch=True):
-            assert v[3:] == (0, 0, 0)
-            assert any(w[:3] == v[:3] and w[5] == 0 for w in mode), (form, v)
+            assert v[3:5] == (0, 0)
+            assert any(w[:3] == v[:3] and w[5] == v[5] for w in mode), (form, v)
         # strip tiles (kind 1): occ = pf = 0, bk the padded contraction length
         strips = [v for v in mode if v[5] == 1]
         assert strips and all(v[3:5] == (0, 0) and v[2] in (16, 32, 64) for v in strips)
@@ -163,20 +163,26 @@ def test_batch_plan_takes_tiles_from_the_table(lib, L, tune):
     alloc = Alloc()
     items = make_items(L, shapes, 1, True, alloc)
     _, st0, _, _ = plan(lib, L, items, len(shapes), 0)
-    bvars = tune.variants("f32", batch=True)
-    modes = [s for s in st0 if s.kind == 0]
-    assert modes
-    # move every mode stage to a tile the executor has, other than its current one
+    allv = tune.variants("f32", batch=True)
+    tiles = [v for v in allv if v[5] == 0]     # stage kind 0 indexes these
+    strips = [v for v in allv if v[5] == 1]    # stage kind 3 indexes these
+    modes = [s for s in st0 if s.kind in (0, 3)]
+    assert modes and any(s.kind == 3 for s in modes)   # short contractions stream
+    # move every mode stage to another executor tile: strips to k-loop tiles
+    # and the other way round where the strip covers m
     for s in modes:
         a = s.m
-        cur = bvars[s.variant // 2]
-        other = next(v for v in bvars if v != cur)
-        tune.set_tile("f32", a.Il, a.m, a.n, a.Ir, other[:3])
+        if s.kind == 3:
+            new = tiles[(s.variant // 2) % len(tiles)]
+        else:
+            new = next((v for v in strips if v[2] >= a.m), tiles[(s.variant // 2 + 1) % len(tiles)])
+        tune.set_tile("f32", a.Il, a.m, a.n, a.Ir, new)
     _, st1, _, _ = plan(lib, L, items, len(shapes), 0)
-    m1 = [s for s in st1 if s.kind == 0]
+    m1 = [s for s in st1 if s.kind in (0, 3)]
     assert len(m1) == len(modes)
     for s in m1:
         a = s.m
         _, tile = tune.lookup("f32", a.Il, a.m, a.n, a.Ir)
-        assert bvars[s.variant // 2][:3] == tile[:3]
+        got = (tiles if s.kind == 0 else strips)[s.variant // 2]
+        assert got[:3] == tile[:3] and got[5] == tile[5]
         assert (s.variant & 1) == (1 if a.Il > 1 else 0)
