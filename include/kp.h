@@ -228,6 +228,18 @@ int kp_expm_f64(const double* A, int64_t n, int64_t count, double tau, double* E
  * tile-timing driver. */
 int kp_force_tile(int nb, int fb, int bk, int occ, int pf, int kind);
 
+/* Process-wide options (not thread-safe; set them before launching).
+ *   KP_OPT_FUSE (default 1): kp_tucker without a cache, on FP32 data with
+ *   the native precision, applies two consecutive modes mu, mu + 1 of its
+ *   planned order in one pass when both are short (m <= 16, n <= 32) and
+ *   I_l > 1, so the intermediate never reaches HBM; the result is the same
+ *   as applying them one after the other (same sums, same rounding).
+ * kp_set_option returns KP_ERR_VALUE for an unknown option or value;
+ * kp_get_option returns the value, or KP_ERR_VALUE. */
+#define KP_OPT_FUSE 1
+int kp_set_option(int option, int value);
+int kp_get_option(int option);
+
 /* Tile table. Before its built-in defaults, the library looks the tile of
  * each mu-mode product up in a process-wide table keyed by the product's
  * form and exact 3-index view; kp_tucker, kp_tucker_backward, kp_mump and
@@ -268,6 +280,9 @@ int kp_tune_clear(void);
  *            kp_tucker_backward recomputes (definition order)
  *         2  kp_tucker_backward's cotangent sweep Q_{mu-1} = Q_mu x_mu L_mu^T
  *            (mu = d..1; when dT is not wanted the sweep stops early)
+ *         3  kp_tucker without a cache, one entry per launch: a fused pass
+ *            over modes mu, mu + 1 (KP_OPT_FUSE) is one entry with kind 2,
+ *            the view of mode mu and the other tile fields 0
  * Writes min(cap, count) entries (out may be NULL if cap is 0) and returns
  * the count; argument errors as kp_tucker_workspace's validation
  * (KP_ERR_NULL for which = 2 with an identity factor, KP_ERR_VALUE for a

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(PKG, "libkp.so")
 KP_MAX_ORDER = 8
 KP_F64, KP_F32 = 0, 1
 KP_PREC_NATIVE, KP_PREC_BF16X3, KP_PREC_BF16X6 = 0, 3, 6
+KP_OPT_FUSE = 1
 
 STATUS = {
     0: "KP_OK", -1: "KP_ERR_NULL", -2: "KP_ERR_ORDER", -3: "KP_ERR_MODE",
@@ -94,6 +95,8 @@ SIGNATURES = {
                                           ctypes.c_int]),
     "kp_tile_variants": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, P(ctypes.c_int32),
                                         ctypes.c_int]),
+    "kp_set_option": (ctypes.c_int, [ctypes.c_int, ctypes.c_int]),
+    "kp_get_option": (ctypes.c_int, [ctypes.c_int]),
     "kp_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "kp_version": (ctypes.c_int, []),
     "kp_last_hip_error": (ctypes.c_int, []),

@@ -8,6 +8,7 @@
 
 #include "kp_common.h"
 #include "kp_internal.h"
+#include "pair_tile.h"
 
 namespace kp {
 
@@ -164,14 +165,47 @@ void make_chain(const kp_tensor& T, const kp_matrix* const* L, bool definition_o
 
 // Workspace for a chain: two ping-pong buffers for the intermediates
 // (steps 1..count-1), buffer (s-1)&1 for the output of step s-1.
+// Workspace for a chain: two ping-pong buffers, each holding the largest
+// intermediate (a fused pass skips a step, so either buffer may receive any
+// intermediate); a launch always writes the buffer its input is not in.
 void chain_ws(const ChainPlan& p, size_t esize, size_t* off1, size_t* total) {
-  size_t b[2] = {0, 0};
+  size_t big = 0;
   for (int s = 1; s < p.count; ++s) {
     const size_t bytes = static_cast<size_t>(p.size[s]) * esize;
-    if (bytes > b[(s - 1) & 1]) b[(s - 1) & 1] = bytes;
+    if (bytes > big) big = bytes;
   }
-  *off1 = align_up(b[0]);
-  *total = *off1 + align_up(b[1]);
+  *off1 = align_up(big);
+  // one intermediate needs one buffer (the first launch writes buffer 0)
+  *total = (p.count > 2 ? 2 : (p.count > 1 ? 1 : 0)) * align_up(big);
+}
+
+// Whether steps s and s + 1 of a chain without a cache run as one fused pass
+// (modes k and k + 1 in that order, both short, I_l > 1); fills the pass's
+// arguments except the tensors.
+bool fuse_step(const ChainPlan& p, int s, int d, const kp_matrix* const* L, int form,
+               tile::PairArgs* pa) {
+  if (!fusion_enabled() || tile_override() || s + 1 >= p.count) return false;
+  const int k = p.order[s];
+  if (p.order[s + 1] != k + 1) return false;
+  const kp_matrix& L1 = *L[k];
+  const kp_matrix& L2 = *L[k + 1];
+  int64_t Il = 1, Ir = 1;
+  for (int j = 0; j < k; ++j) Il *= p.dims[s][j];
+  for (int j = k + 2; j < d; ++j) Ir *= p.dims[s][j];
+  if (!pair_eligible(form, Il, L1.cols, L2.cols, L1.rows, L2.rows)) return false;
+  pa->L1 = L1.data;
+  pa->L2 = L2.data;
+  pa->Il = Il;
+  pa->m1 = L1.cols;
+  pa->m2 = L2.cols;
+  pa->n1 = L1.rows;
+  pa->n2 = L2.rows;
+  pa->Ir = Ir;
+  pa->rs1 = L1.rs;
+  pa->cs1 = L1.cs;
+  pa->rs2 = L2.rs;
+  pa->cs2 = L2.cs;
+  return true;
 }
 
 int validate_tucker_args(const kp_tensor* T, const kp_matrix* const* L, int prec) {
@@ -351,17 +385,31 @@ int kp_tucker(const kp_tensor* T, const kp_matrix* const* L, kp_tensor* S, int p
   }
   const void* src = T->data;
   size_t cache_off = 0;
+  int cur = -1;  // ping-pong buffer holding src (-1: src is T or a cache slot)
+  // the launch that ends at step s writes S (last step), its cache slot, or
+  // the ping-pong buffer that does not hold its input
+  auto dst_of = [&](int s) -> void* {
+    if (s == p.count - 1) return S->data;
+    if (cache) return static_cast<char*>(cache) + cache_off;
+    cur = cur == 0 ? 1 : 0;
+    return static_cast<char*>(ws) + (cur ? off1 : 0);
+  };
   for (int s = 0; s < p.count; ++s) {
-    void* dst;
-    if (s == p.count - 1) {
-      dst = S->data;
-    } else if (cache) {
-      dst = static_cast<char*>(cache) + cache_off;
-      cache_off += align_up(static_cast<size_t>(p.size[s + 1]) * es);
-    } else {
-      dst = static_cast<char*>(ws) + ((s & 1) ? off1 : 0);
-    }
     const int k = p.order[s];
+    // steps s and s + 1 on modes k and k + 1: one fused pass when possible
+    // (never with a cache, which must hold every partial product)
+    tile::PairArgs pa;
+    if (!cache && fuse_step(p, s, T->d, L, form, &pa)) {
+      pa.X = src;
+      pa.Y = dst_of(s + 1);
+      st = hip_status(launch_pair(form, pa, stream));
+      if (st) return st;
+      src = pa.Y;
+      ++s;
+      continue;
+    }
+    void* dst = dst_of(s);
+    if (cache && s < p.count - 1) cache_off += align_up(static_cast<size_t>(p.size[s + 1]) * es);
     const ModeArgs a = mode_args(src, dst, p.dims[s], T->d, k, *L[k], 0);
     st = hip_status(launch_mode(form, a, tile_override(), stream));
     if (st) return st;
@@ -508,7 +556,7 @@ int kp_tucker_products(const kp_tensor* T, const kp_matrix* const* L, int prec, 
                        kp_tune_entry* out, int cap) {
   int st = validate_tucker_args(T, L, prec);
   if (st) return st;
-  if (which < 0 || which > 2) return KP_ERR_VALUE;
+  if (which < 0 || which > 3) return KP_ERR_VALUE;
   if (cap > 0 && !out) return KP_ERR_NULL;
   const int d = T->d;
   if (which == 2)
@@ -537,12 +585,29 @@ int kp_tucker_products(const kp_tensor* T, const kp_matrix* const* L, int prec, 
     }
     ++count;
   };
-  if (which < 2) {
+  if (which < 2 || which == 3) {
     ChainPlan p;
     make_chain(*T, L, which == 1, &p);
     for (int s = 0; s < p.count; ++s) {
       const int k = p.order[s];
-      emit(mode_args(nullptr, nullptr, p.dims[s], d, k, *L[k], 0));
+      const ModeArgs a = mode_args(nullptr, nullptr, p.dims[s], d, k, *L[k], 0);
+      tile::PairArgs pa;
+      if (which == 3 && fuse_step(p, s, d, L, form, &pa)) {
+        if (count < cap) {
+          kp_tune_entry& e = out[count];
+          memset(&e, 0, sizeof(e));
+          e.form = form;
+          e.Il = a.Il;
+          e.m = a.m;
+          e.n = a.n;
+          e.Ir = a.Ir;
+          e.kind = 2;
+        }
+        ++count;
+        ++s;
+        continue;
+      }
+      emit(a);
     }
   } else {
     int64_t qdims[KP_MAX_ORDER];

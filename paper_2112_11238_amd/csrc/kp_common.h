@@ -64,4 +64,14 @@ bool strip_resolve(int form, const ModeTile& t, ModeTile* out);
 int list_strip_variants(int form, int32_t* out, int cap);
 hipError_t launch_strip(int form, const ModeArgs& a, const ModeTile& t, hipStream_t stream);
 
+// Fused pair of consecutive products, modes mu and mu + 1 (pair_tile.h,
+// pair_kernels.hip): whether a form and shape have a pair kernel, and the
+// launch. The product of mode mu has the sizes (Il, m1) -> n1, that of
+// mode mu + 1 then (Il*n1, m2) -> n2.
+namespace tile {
+struct PairArgs;
+}
+bool pair_eligible(int form, int64_t Il, int64_t m1, int64_t m2, int64_t n1, int64_t n2);
+hipError_t launch_pair(int form, const tile::PairArgs& a, hipStream_t stream);
+
 }  // namespace kp

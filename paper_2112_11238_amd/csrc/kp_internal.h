@@ -8,6 +8,8 @@ namespace kp {
 
 // Tile forced by kp_force_tile (nullptr: use the tuned / default choice).
 const ModeTile* tile_override();
+// KP_OPT_FUSE: consecutive short modes fused in kp_tucker.
+bool fusion_enabled();
 
 int hip_status(hipError_t e);
 // Three-index view arguments for the product of mode mu0 (0-based) of a

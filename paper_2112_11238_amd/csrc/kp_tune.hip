@@ -46,6 +46,12 @@ void fill(kp_tune_entry* e, const Key& k, const ModeTile& t) {
 
 const ModeTile* tile_override() { return g_force ? &g_forced : nullptr; }
 
+namespace {
+bool g_fuse = true;
+}  // namespace
+
+bool fusion_enabled() { return g_fuse; }
+
 bool tuned_tile(int form, int64_t Il, int64_t m, int64_t n, int64_t Ir, ModeTile* out) {
   std::lock_guard<std::mutex> lock(g_mu);
   const auto& t = table();
@@ -73,6 +79,20 @@ extern "C" int kp_force_tile(int nb, int fb, int bk, int occ, int pf, int kind) 
   kp::g_forced.pf = pf;
   kp::g_force = true;
   return KP_OK;
+}
+
+extern "C" int kp_set_option(int option, int value) {
+  if (option == KP_OPT_FUSE) {
+    if (value != 0 && value != 1) return KP_ERR_VALUE;
+    kp::g_fuse = value != 0;
+    return KP_OK;
+  }
+  return KP_ERR_VALUE;
+}
+
+extern "C" int kp_get_option(int option) {
+  if (option == KP_OPT_FUSE) return kp::g_fuse ? 1 : 0;
+  return KP_ERR_VALUE;
 }
 
 extern "C" int kp_tune_set(const kp_tune_entry* e) {

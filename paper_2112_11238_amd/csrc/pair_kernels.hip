@@ -1,0 +1,76 @@
+// Fused pairs of consecutive mu-mode products (pair_tile.h), FP32 form:
+// the memory-bound products of short modes (m <= 16, n <= 32) on the
+// strided layout (I_l > 1). One launch per piece of the outer index b that
+// stays below 2^31 bytes; workgroups stride over 16-fiber tiles.
+#include <mutex>
+#include <unordered_map>
+
+#include "kp_common.h"
+#include "kp_internal.h"
+#include "pair_tile.h"
+
+namespace kp {
+namespace {
+
+using namespace tile;
+
+constexpr int kKP1 = 16, kKP2 = 16, kNB1 = 2, kNB2 = 2;
+
+__global__ __launch_bounds__(kThreads, 2) void pair_kernel_f32(PairArgs a, int64_t ntiles) {
+  __shared__ __attribute__((aligned(16))) char
+      lds[pair_lds_bytes<FORM_F32, kKP1, kKP2, kNB1, kNB2>()];
+  pair_run<FORM_F32, kKP1, kKP2, kNB1, kNB2>(a, blockIdx.x, gridDim.x, ntiles, lds);
+}
+
+int pair_slots() {
+  static std::mutex mu;
+  static int slots = 0;
+  std::lock_guard<std::mutex> lock(mu);
+  if (slots == 0) {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus < 1)
+      cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per, reinterpret_cast<const void*>(pair_kernel_f32), kThreads, 0) != hipSuccess ||
+        per < 1)
+      per = 1;
+    slots = cus * per;
+  }
+  return slots;
+}
+
+}  // namespace
+
+bool pair_eligible(int form, int64_t Il, int64_t m1, int64_t m2, int64_t n1, int64_t n2) {
+  return form == FORM_F32 && Il > 1 && m1 >= 1 && m2 >= 1 && m1 <= kKP1 && m2 <= kKP2 &&
+         n1 >= 1 && n2 >= 1 && n1 <= 16 * kNB1 && n2 <= 16 * kNB2;
+}
+
+hipError_t launch_pair(int form, const PairArgs& a, hipStream_t stream) {
+  if (!pair_eligible(form, a.Il, a.m1, a.m2, a.n1, a.n2)) return hipErrorInvalidValue;
+  if (a.Il * a.Ir == 0) return hipSuccess;
+  const int64_t es = 4;
+  const int64_t mm = a.m1 * a.m2, nn = a.n1 * a.n2;
+  const int64_t slab = a.Il * (mm > nn ? mm : nn) * es;  // bytes per b
+  const int64_t limit = static_cast<int64_t>(1) << 31;
+  if (slab >= limit) return hipErrorInvalidValue;
+  const int64_t per = (limit - 1) / slab;
+  for (int64_t b0 = 0; b0 < a.Ir; b0 += per) {
+    PairArgs p = a;
+    p.Ir = (a.Ir - b0 < per) ? a.Ir - b0 : per;
+    p.X = static_cast<const char*>(a.X) + b0 * a.Il * mm * es;
+    p.Y = static_cast<char*>(a.Y) + b0 * a.Il * nn * es;
+    const int64_t ntiles = (p.Il * p.Ir + kPairFibers - 1) / kPairFibers;
+    int64_t grid = pair_slots();
+    if (grid > ntiles) grid = ntiles;
+    hipLaunchKernelGGL(pair_kernel_f32, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0,
+                       stream, p, ntiles);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace kp

@@ -110,14 +110,15 @@ def load(path):
     return len(rec["entries"])
 
 
-WHICH = {"forward": 0, "forward_cached": 1, "backward": 2}
+WHICH = {"forward": 0, "forward_cached": 1, "backward": 2, "launches": 3}
 
 
 def products(T, Ls, prec="native", which="forward"):
     """The mu-mode products a call launches, in launch order, each a dict with
     its view and current tile. which: "forward" (kp_tucker), "forward_cached"
     (kp_tucker with a cache / the backward's recomputed partials, and the
-    batched executor's forward), "backward" (the cotangent sweep)."""
+    batched executor's forward), "backward" (the cotangent sweep), "launches"
+    (kp_tucker's launches: a fused pair of modes is one entry of kind 2)."""
     Tc = _canon(T)
     td = _tdesc(Tc, True)
     arr = _mlist([None if L is None else _mdesc(L) for L in Ls][::-1])

@@ -1,0 +1,75 @@
+"""Fused pairs of consecutive modes (KP_OPT_FUSE): the fused Tucker operator
+equals the mode-by-mode one bitwise (same sums, same rounding of the
+intermediate) and the FP64 oracle within the chain bound."""
+import numpy as np
+import pytest
+import torch
+
+import kp_workloads
+import oracle
+from gpu_util import cast64, chain_bound, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    # torch shapes m, n; at least one pair of consecutive short modes with I_l > 1
+    ((6, 7, 16, 16, 16), (6, 7, 24, 24, 24)),
+    ((5, 9, 13, 11, 7), (6, 10, 15, 14, 9)),
+    ((3, 16, 16, 16, 16), (3, 24, 24, 24, 24)),
+    ((40, 2, 3, 33), (41, 3, 4, 34)),
+    ((30, 3, 5, 7), (31, 4, 6, 9)),
+]
+
+
+@pytest.fixture()
+def kp():
+    import paper_2112_11238_amd as kp
+    from paper_2112_11238_amd import _lib
+    lib = _lib.load()
+    yield kp
+    lib.kp_set_option(_lib.KP_OPT_FUSE, 1)
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_fused_equals_unfused_and_oracle(kp, case):
+    from paper_2112_11238_amd import _lib, tune
+    lib = _lib.load()
+    m, n = CASES[case]
+    T, Ls = kp_workloads.random_problem(6000 + case, m, n)
+    Td = to_dev(T, torch.float32)
+    Ld = [to_dev(L, torch.float32) for L in Ls]
+    if case == 1:   # a factor given as a transposed (non-contiguous) view
+        Ld[3] = Ld[3].t().contiguous().t()
+    launches = tune.products(Td, Ld, which="launches")
+    assert any(p["kind"] == 2 for p in launches), launches
+    say("fusion", m, n, [p["kind"] for p in launches])
+    S_f = kp.tucker(Td, Ld)
+    torch.cuda.synchronize()
+    assert lib.kp_set_option(_lib.KP_OPT_FUSE, 0) == 0
+    assert all(p["kind"] != 2 for p in tune.products(Td, Ld, which="launches"))
+    S_u = kp.tucker(Td, Ld)
+    torch.cuda.synchronize()
+    assert torch.equal(S_f, S_u)
+    T64, L64 = cast64(T, torch.float32), [cast64(L, torch.float32) for L in Ls]
+    ref = oracle.tucker(T64, L64)
+    assert np.all(np.abs(S_f.double().cpu().numpy() - ref) <= chain_bound(T64, L64, "native",
+                                                                         torch.float32))
+
+
+def test_fused_interp6d_full_size(kp):
+    """The 16^6 -> 24^6 interpolation: fused launches on the largest modes,
+    result equal to the unfused chain."""
+    from paper_2112_11238_amd import _lib, tune
+    lib = _lib.load()
+    T, Ls = kp_workloads.interp6d(seed=0)
+    Td = to_dev(T, torch.float32)
+    Ld = [to_dev(L, torch.float32) for L in Ls]
+    kinds = [p["kind"] for p in tune.products(Td, Ld, which="launches")]
+    say("fusion interp6d", kinds)
+    assert kinds.count(2) == 2
+    S_f = kp.tucker(Td, Ld)
+    torch.cuda.synchronize()
+    lib.kp_set_option(_lib.KP_OPT_FUSE, 0)
+    S_u = kp.tucker(Td, Ld)
+    torch.cuda.synchronize()
+    assert torch.equal(S_f, S_u)

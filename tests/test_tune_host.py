@@ -186,3 +186,29 @@ def test_batch_plan_takes_tiles_from_the_table(lib, L, tune):
         got = (tiles if s.kind == 0 else strips)[s.variant // 2]
         assert got[:3] == tile[:3] and got[5] == tile[5]
         assert (s.variant & 1) == (1 if a.Il > 1 else 0)
+
+
+def test_fusion_option_and_reported_launches(lib, L, tune):
+    assert lib.kp_get_option(L.KP_OPT_FUSE) == 1
+    assert lib.kp_set_option(L.KP_OPT_FUSE, 2) == -9
+    assert lib.kp_set_option(99, 0) == -9 and lib.kp_get_option(99) == -9
+    # canonical dims (16, 16, 16, 7, 6): the square modes go first (fewer
+    # flops), then modes 0, 1, 2; (3, 4) and (1, 2) are fusable pairs (I_l > 1,
+    # m <= 16, n <= 32), mode 0 (I_l = 1) runs alone
+    T = torch.zeros((6, 7, 16, 16, 16), dtype=torch.float32)
+    Ls = [torch.zeros((6, 6)), torch.zeros((7, 7))] + [torch.zeros((24, 16))] * 3
+    try:
+        got = tune.products(T, Ls, which="launches")
+        assert [p["kind"] for p in got] == [2, 1, 2]
+        assert [(p["Il"], p["m"], p["n"]) for p in got] == [(4096, 7, 7), (1, 16, 24),
+                                                              (24, 16, 24)]
+        assert lib.kp_set_option(L.KP_OPT_FUSE, 0) == 0
+        assert [p["kind"] for p in tune.products(T, Ls, which="launches")] == [1] * 5
+        # FP64 and the split forms are never fused
+        assert lib.kp_set_option(L.KP_OPT_FUSE, 1) == 0
+        T64 = T.double()
+        L64 = [x.double() for x in Ls]
+        assert all(p["kind"] != 2 for p in tune.products(T64, L64, which="launches"))
+        assert all(p["kind"] != 2 for p in tune.products(T, Ls, "bf16x3", which="launches"))
+    finally:
+        lib.kp_set_option(L.KP_OPT_FUSE, 1)
