@@ -98,6 +98,9 @@ const Variant kVariants[] = {
     // prefetch distance 2
     KP_VP(FORM_F64, 7, 1, 16, 2, 2), KP_VP(FORM_F64, 4, 1, 16, 2, 2),
     KP_VP(FORM_F64, 8, 1, 16, 2, 2), KP_VP(FORM_F64, 7, 1, 8, 2, 2),
+    KP_V(FORM_F64, 7, 1, 8, 2), KP_V(FORM_F64, 7, 1, 8, 3), KP_V(FORM_F64, 13, 1, 8, 2),
+    KP_V(FORM_F64, 7, 1, 16, 3), KP_V(FORM_F64, 4, 1, 8, 3), KP_V(FORM_F64, 8, 1, 8, 3),
+    KP_V(FORM_F64, 2, 2, 8, 3),
     KP_VP(FORM_F32, 8, 1, 16, 2, 2), KP_VP(FORM_F32, 4, 1, 16, 2, 2),
     KP_VP(FORM_F32, 7, 1, 16, 2, 2), KP_VP(FORM_F32, 13, 1, 16, 2, 2),
     KP_VP(FORM_BF16X3, 4, 1, 32, 2, 2), KP_VP(FORM_BF16X3, 8, 1, 32, 2, 2),
@@ -113,9 +116,11 @@ const Variant* find_variant(int form, const ModeTile& t) {
   return nullptr;
 }
 
-// Default tiles, chosen from tile sweeps on cube200 (m = n = 200) and small
-// modes: FP64 favours 7 blocks along n at 3 waves per SIMD, FP32 8 blocks,
-// the BF16 split forms 4 blocks (n tiles re-read their fibers from L2).
+// Default tiles, chosen from tile sweeps on cube200 (m = n = 200), heat128
+// (n = 128) and small modes: FP64 favours 7 (or, at n = 128, 4) blocks along
+// n with 8-wide k chunks (small LDS and register footprint: 4 waves/SIMD),
+// FP32 4 blocks, the BF16 split forms 4 blocks with two fiber blocks per
+// wave for BF16x3. Short contractions (m <= 64) take strip tiles.
 ModeTile pick_tile(int form, int64_t m, int64_t n) {
   ModeTile t{};
   if (strip_default(form, m, n, &t)) return t;
@@ -125,21 +130,22 @@ ModeTile pick_tile(int form, int64_t m, int64_t n) {
     t.bk = 16;
     if (n <= 16) { t.nb = 1; t.fb = 4; }
     else if (n <= 32) { t.nb = 2; t.fb = 2; }
-    else if (n <= 64) { t.nb = 4; t.fb = 1; }
-    else if (n <= 112) { t.nb = 7; t.fb = 1; }
-    else if (n <= 128) { t.nb = 8; t.fb = 1; }
-    else { t.nb = 7; t.fb = 1; }
+    else {
+      t.bk = 8;
+      t.occ = 3;
+      t.fb = 1;
+      t.nb = (n <= 64 || (n > 112 && n <= 128)) ? 4 : 7;
+    }
   } else if (form == FORM_F32) {
     t.bk = 16;
     if (n <= 16) { t.nb = 1; t.fb = 4; }
     else if (n <= 32) { t.nb = 2; t.fb = 2; }
-    else if (n <= 64) { t.nb = 4; t.fb = 1; }
-    else { t.nb = 8; t.fb = 1; }
+    else { t.nb = 4; t.fb = 1; }
   } else {
     t.bk = 32;
     if (n <= 16) { t.nb = 1; t.fb = 4; }
     else if (n <= 32) { t.nb = 2; t.fb = 2; }
-    else { t.nb = 4; t.fb = 1; }
+    else { t.nb = 4; t.fb = form == FORM_BF16X3 ? 2 : 1; }
   }
   return t;
 }

@@ -314,6 +314,8 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t bx, int64_t
     else
       load_chunk(ch * BK, Checked{}, set);
   };
+  // n blocks of this tile that hold rows below n (the rest are skipped)
+  const int nbu = static_cast<int>((n - i0 + 15) / 16);
   auto compute = [&](int buf) {
 #pragma unroll
     for (int kk = 0; kk < BK; kk += MK) {
@@ -326,6 +328,7 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t bx, int64_t
               &sX[buf][p][w * 16 * FB + fb * 16 + c][kk + KV * g]);
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
+        if (nb >= nbu) break;
         FragT la[P];
 #pragma unroll
         for (int p = 0; p < P; ++p)

@@ -121,6 +121,8 @@ TILES = {
 }
 # prefetch-distance-2 variants (nb, fb, bk, occ, pf)
 TILES["native64"] += [(7, 1, 16, 2, 2), (4, 1, 16, 2, 2), (8, 1, 16, 2, 2), (7, 1, 8, 2, 2)]
+TILES["native64"] += [(7, 1, 8, 2), (7, 1, 8, 3), (13, 1, 8, 2), (7, 1, 16, 3), (4, 1, 8, 3),
+                      (8, 1, 8, 3), (2, 2, 8, 3)]
 TILES["native32"] += [(8, 1, 16, 2, 2), (4, 1, 16, 2, 2), (7, 1, 16, 2, 2), (13, 1, 16, 2, 2)]
 TILES["bf16x3"] += [(4, 1, 32, 2, 2), (8, 1, 32, 2, 2)]
 TILES["bf16x6"] += [(4, 1, 32, 2, 2), (8, 1, 32, 2, 2)]

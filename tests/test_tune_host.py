@@ -79,7 +79,7 @@ def test_set_lookup_list_clear(lib, L, tune):
     tune.clear()
     # default first
     tuned, tile = tune.lookup("f64", 40, 200, 200, 200)
-    assert not tuned and tile[:3] == (7, 1, 16)
+    assert not tuned and tile[:3] == (7, 1, 8)
     tune.set_tile("f64", 40, 200, 200, 200, (4, 1, 16))
     tuned, tile = tune.lookup("f64", 40, 200, 200, 200)
     assert tuned and tile[:3] == (4, 1, 16) and tile[3] > 0 and tile[4:] == (1, 0)  # resolved
