@@ -13,8 +13,9 @@ through the C-ABI (kp_tucker), in each arithmetic form:
 
 Each form's error against the FP64 oracle (max-norm relative, the paper's
 metric) is reported with it. Each mu-mode product is also timed alone
-(kp_mump, HIP events around every launch on the launch stream); the FP64
-per-launch average gives the roofline entry of the dominant kernel.
+(kp_mump, launches back to back between two HIP events on the launch
+stream); the FP64 per-launch average gives the roofline entry of the
+dominant kernel.
 The oracle (numpy FP64 on the host) is timed on a bounded sample of the same
 workload as the CPU baseline. Prints one JSON line.
 """
@@ -207,20 +208,22 @@ def main():
         step_ms = [ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)]
         total_ms = ev[0].elapsed_time(ev[-1])
         ms = total_ms / args.steps
-        # each mu-mode product alone (kp_mump), events around every launch
+        # each mu-mode product alone (kp_mump): `steps` launches back to back
+        # on the launch stream between two HIP events (the average includes
+        # the launch gaps, a few us, so it is an upper bound of the kernel time)
         per_mode = {}
         for mu in (1, 2, 3):
             out = torch.empty_like(Td)
             for _ in range(2):
                 kp.mump(Td, Lds[mu - 1], mu, prec=prec, out=out)
-            e = [torch.cuda.Event(enable_timing=True) for _ in range(2 * args.steps)]
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
             for k in range(args.steps):
-                e[2 * k].record()
                 kp.mump(Td, Lds[mu - 1], mu, prec=prec, out=out)
-                e[2 * k + 1].record()
+            e1.record()
             torch.cuda.synchronize()
-            d = [e[2 * k].elapsed_time(e[2 * k + 1]) for k in range(args.steps)]
-            per_mode[mu] = statistics.mean(d)
+            per_mode[mu] = e0.elapsed_time(e1) / args.steps
         peak = PEAK["f64"] if dt == "f64" else (PEAK["f32"] if prec == "native" else PEAK["bf16"])
         tflops = flops / (ms * 1e-3) / 1e12
         mfma_tflops = tflops * (1 if prec == "native" else int(prec[-1]))
