@@ -46,13 +46,13 @@ __device__ __forceinline__ void xcd_tile(int64_t gx, int64_t gy, int64_t* bx, in
   *bx = logical / gy;
 }
 
-template <int FORM, int NB, int FB, int BK, int OCC, int PF, bool INNER>
+template <int FORM, int NB, int FB, int BK, int OCC, int PF, bool INNER, bool VEC>
 __global__ __launch_bounds__(kThreads, OCC) void mode_kernel(ModeArgs a, int64_t gx,
                                                              int64_t gy) {
   __shared__ __attribute__((aligned(16))) char lds[mode_lds_bytes<FORM, NB, FB, BK>()];
   int64_t bx, by;
   xcd_tile(gx, gy, &bx, &by);
-  mode_tile<FORM, NB, FB, BK, INNER, PF>(a, bx, by, lds);
+  mode_tile<FORM, NB, FB, BK, INNER, PF, VEC>(a, bx, by, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -60,51 +60,44 @@ __global__ __launch_bounds__(kThreads, OCC) void mode_kernel(ModeArgs a, int64_t
 // ---------------------------------------------------------------------------
 using KernelFn = void (*)(ModeArgs, int64_t, int64_t);
 
+// kernel[inner][vec]
 struct Variant {
   int form, nb, fb, bk, occ, pf;
-  KernelFn lead, inner;
+  KernelFn kernel[2][2];
 };
 
-#define KP_VP(FORM, NB, FB, BK, OCC, PF)                                      \
-  {FORM, NB, FB, BK, OCC, PF, mode_kernel<FORM, NB, FB, BK, OCC, PF, false>, \
-   mode_kernel<FORM, NB, FB, BK, OCC, PF, true>}
+#define KP_VP(FORM, NB, FB, BK, OCC, PF)                                           \
+  {FORM, NB, FB, BK, OCC, PF,                                                       \
+   {{mode_kernel<FORM, NB, FB, BK, OCC, PF, false, false>,                          \
+     mode_kernel<FORM, NB, FB, BK, OCC, PF, false, true>},                          \
+    {mode_kernel<FORM, NB, FB, BK, OCC, PF, true, false>,                           \
+     mode_kernel<FORM, NB, FB, BK, OCC, PF, true, true>}}}
 #define KP_V(FORM, NB, FB, BK, OCC) KP_VP(FORM, NB, FB, BK, OCC, 1)
 
 const Variant kVariants[] = {
     // FP64
-    KP_V(FORM_F64, 1, 4, 16, 1), KP_V(FORM_F64, 2, 4, 16, 1), KP_V(FORM_F64, 2, 2, 16, 2),
-    KP_V(FORM_F64, 4, 2, 16, 2), KP_V(FORM_F64, 4, 1, 16, 2), KP_V(FORM_F64, 8, 1, 16, 2),
-    KP_V(FORM_F64, 8, 2, 16, 1), KP_V(FORM_F64, 13, 1, 16, 1), KP_V(FORM_F64, 13, 1, 16, 2),
-    KP_V(FORM_F64, 16, 1, 16, 1), KP_V(FORM_F64, 7, 1, 16, 2), KP_V(FORM_F64, 7, 1, 32, 2),
-    KP_V(FORM_F64, 13, 1, 32, 1), KP_V(FORM_F64, 7, 2, 16, 1),
+    KP_V(FORM_F64, 1, 4, 16, 1), KP_V(FORM_F64, 2, 2, 16, 2), KP_V(FORM_F64, 4, 1, 16, 2),
+    KP_V(FORM_F64, 7, 1, 16, 2), KP_V(FORM_F64, 8, 1, 16, 2), KP_V(FORM_F64, 13, 1, 16, 2),
+    KP_V(FORM_F64, 7, 1, 8, 2), KP_V(FORM_F64, 7, 1, 8, 3), KP_V(FORM_F64, 4, 1, 8, 3),
+    KP_V(FORM_F64, 8, 1, 8, 3), KP_V(FORM_F64, 2, 2, 8, 3), KP_V(FORM_F64, 13, 1, 8, 2),
+    KP_VP(FORM_F64, 7, 1, 16, 2, 2), KP_VP(FORM_F64, 7, 1, 8, 2, 2),
+    KP_VP(FORM_F64, 4, 1, 16, 2, 2),
     // FP32
     KP_V(FORM_F32, 1, 4, 16, 2), KP_V(FORM_F32, 2, 4, 16, 2), KP_V(FORM_F32, 2, 2, 16, 2),
     KP_V(FORM_F32, 4, 2, 16, 2), KP_V(FORM_F32, 4, 1, 16, 2), KP_V(FORM_F32, 8, 1, 16, 2),
-    KP_V(FORM_F32, 8, 2, 16, 2), KP_V(FORM_F32, 13, 1, 16, 2), KP_V(FORM_F32, 16, 1, 16, 2),
-    KP_V(FORM_F32, 13, 1, 32, 2), KP_V(FORM_F32, 13, 1, 32, 1), KP_V(FORM_F32, 13, 2, 16, 1),
-    KP_V(FORM_F32, 7, 2, 16, 2), KP_V(FORM_F32, 7, 1, 32, 2),
+    KP_V(FORM_F32, 7, 2, 16, 2), KP_V(FORM_F32, 13, 1, 16, 2),
+    KP_VP(FORM_F32, 4, 1, 16, 2, 2), KP_VP(FORM_F32, 7, 1, 16, 2, 2),
+    KP_VP(FORM_F32, 8, 1, 16, 2, 2),
     // BF16 x3
     KP_V(FORM_BF16X3, 1, 4, 32, 2), KP_V(FORM_BF16X3, 2, 4, 32, 2), KP_V(FORM_BF16X3, 2, 2, 32, 2),
     KP_V(FORM_BF16X3, 4, 2, 32, 2), KP_V(FORM_BF16X3, 4, 1, 32, 2), KP_V(FORM_BF16X3, 8, 1, 32, 2),
-    KP_V(FORM_BF16X3, 8, 2, 32, 1), KP_V(FORM_BF16X3, 13, 1, 32, 1), KP_V(FORM_BF16X3, 16, 1, 32, 1),
-    KP_V(FORM_BF16X3, 13, 1, 32, 2), KP_V(FORM_BF16X3, 7, 1, 32, 2), KP_V(FORM_BF16X3, 4, 2, 64, 2),
-    KP_V(FORM_BF16X3, 1, 2, 32, 2), KP_V(FORM_BF16X3, 2, 1, 32, 2),
+    KP_V(FORM_BF16X3, 7, 1, 32, 2), KP_V(FORM_BF16X3, 1, 2, 32, 2), KP_V(FORM_BF16X3, 2, 1, 32, 2),
+    KP_VP(FORM_BF16X3, 4, 1, 32, 2, 2),
     // BF16 x6
     KP_V(FORM_BF16X6, 1, 4, 32, 2), KP_V(FORM_BF16X6, 2, 4, 32, 2), KP_V(FORM_BF16X6, 2, 2, 32, 2),
     KP_V(FORM_BF16X6, 4, 2, 32, 2), KP_V(FORM_BF16X6, 4, 1, 32, 2), KP_V(FORM_BF16X6, 8, 1, 32, 2),
-    KP_V(FORM_BF16X6, 8, 2, 32, 1), KP_V(FORM_BF16X6, 13, 1, 32, 1), KP_V(FORM_BF16X6, 16, 1, 32, 1),
-    KP_V(FORM_BF16X6, 13, 1, 32, 2), KP_V(FORM_BF16X6, 7, 1, 32, 2),
     KP_V(FORM_BF16X6, 1, 2, 32, 2), KP_V(FORM_BF16X6, 2, 1, 32, 2),
-    // prefetch distance 2
-    KP_VP(FORM_F64, 7, 1, 16, 2, 2), KP_VP(FORM_F64, 4, 1, 16, 2, 2),
-    KP_VP(FORM_F64, 8, 1, 16, 2, 2), KP_VP(FORM_F64, 7, 1, 8, 2, 2),
-    KP_V(FORM_F64, 7, 1, 8, 2), KP_V(FORM_F64, 7, 1, 8, 3), KP_V(FORM_F64, 13, 1, 8, 2),
-    KP_V(FORM_F64, 7, 1, 16, 3), KP_V(FORM_F64, 4, 1, 8, 3), KP_V(FORM_F64, 8, 1, 8, 3),
-    KP_V(FORM_F64, 2, 2, 8, 3),
-    KP_VP(FORM_F32, 8, 1, 16, 2, 2), KP_VP(FORM_F32, 4, 1, 16, 2, 2),
-    KP_VP(FORM_F32, 7, 1, 16, 2, 2), KP_VP(FORM_F32, 13, 1, 16, 2, 2),
-    KP_VP(FORM_BF16X3, 4, 1, 32, 2, 2), KP_VP(FORM_BF16X3, 8, 1, 32, 2, 2),
-    KP_VP(FORM_BF16X6, 4, 1, 32, 2, 2), KP_VP(FORM_BF16X6, 8, 1, 32, 2, 2),
+    KP_VP(FORM_BF16X6, 4, 1, 32, 2, 2),
 };
 
 const Variant* find_variant(int form, const ModeTile& t) {
@@ -118,9 +111,10 @@ const Variant* find_variant(int form, const ModeTile& t) {
 
 // Default tiles, chosen from tile sweeps on cube200 (m = n = 200), heat128
 // (n = 128) and small modes: FP64 favours 7 (or, at n = 128, 4) blocks along
-// n with 8-wide k chunks (small LDS and register footprint: 4 waves/SIMD),
-// FP32 4 blocks, the BF16 split forms 4 blocks with two fiber blocks per
-// wave for BF16x3. Short contractions (m <= 64) take strip tiles.
+// n with 8-wide k chunks (small LDS and register footprint: 4 waves/SIMD);
+// FP32 7 blocks (8 at n <= 128) with two chunks of loads in flight; the
+// BF16 split forms 4 blocks (BF16x6 with two chunks in flight). Short
+// contractions (m <= 64) take strip tiles.
 ModeTile pick_tile(int form, int64_t m, int64_t n) {
   ModeTile t{};
   if (strip_default(form, m, n, &t)) return t;
@@ -140,12 +134,13 @@ ModeTile pick_tile(int form, int64_t m, int64_t n) {
     t.bk = 16;
     if (n <= 16) { t.nb = 1; t.fb = 4; }
     else if (n <= 32) { t.nb = 2; t.fb = 2; }
-    else { t.nb = 4; t.fb = 1; }
+    else if (n <= 64) { t.nb = 4; t.fb = 1; }
+    else { t.nb = n <= 128 ? 8 : 7; t.fb = 1; t.pf = 2; }
   } else {
     t.bk = 32;
     if (n <= 16) { t.nb = 1; t.fb = 4; }
     else if (n <= 32) { t.nb = 2; t.fb = 2; }
-    else { t.nb = 4; t.fb = form == FORM_BF16X3 ? 2 : 1; }
+    else { t.nb = 4; t.fb = 1; t.pf = form == FORM_BF16X6 ? 2 : 0; }
   }
   return t;
 }
@@ -216,6 +211,13 @@ hipError_t launch_mode(int form, const ModeArgs& a, const ModeTile* force,
   const int64_t per = (limit - 1) / (slab > 0 ? slab : 1);
   const int64_t bf = 64 * t.fb;
   const int64_t bn = 16 * t.nb;
+  // 16-byte group loads: L k-contiguous with 16-byte aligned rows, m a
+  // multiple of the group (so the k tail is whole groups), and for the lead
+  // layout X rows (m elements) 16-byte aligned too
+  const int64_t kv = form == FORM_F64 ? 2 : (form == FORM_F32 ? 4 : 8);
+  const bool vec_l = a.cs == 1 && (a.rs * es) % 16 == 0 && a.m % kv == 0 &&
+                     reinterpret_cast<uintptr_t>(a.L) % 16 == 0;
+  const bool xrow16 = (a.m * es) % 16 == 0;
   for (int64_t b0 = 0; b0 < a.Ir; b0 += per) {
     ModeArgs p = a;
     p.Ir = (a.Ir - b0 < per) ? a.Ir - b0 : per;
@@ -231,8 +233,10 @@ hipError_t launch_mode(int form, const ModeArgs& a, const ModeTile* force,
     const int64_t gy = (p.n + bn - 1) / bn;
     // one-dimensional grid: its size in work-items must fit 32 bits
     if (gx * gy > 0xffffffffLL / kThreads) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL(inner ? v->inner : v->lead, dim3(static_cast<unsigned>(gx * gy)),
-                       dim3(kThreads), 0, stream, p, gx, gy);
+    const bool vec = vec_l && (inner || (xrow16 && reinterpret_cast<uintptr_t>(p.X) % 16 == 0));
+    hipLaunchKernelGGL(v->kernel[inner ? 1 : 0][vec ? 1 : 0],
+                       dim3(static_cast<unsigned>(gx * gy)), dim3(kThreads), 0, stream, p, gx,
+                       gy);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -43,6 +43,22 @@ __device__ __forceinline__ void split_bf16(float x, __bf16 (&o)[P]) {
   }
 }
 
+// Buffer resource word 3 for raw (unformatted, unswizzled) buffers on the
+// gfx9 family; loads at offsets at or past the resource's size return zero.
+constexpr int kBufferFlags = 0x00020000;
+
+template <typename G>
+__device__ __forceinline__ G buffer_load(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
+  if constexpr (sizeof(G) == 8) {
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+    const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(rs, static_cast<int>(off), 0, 0);
+    return __builtin_bit_cast(G, v);
+  } else {
+    const unsigned int v = __builtin_amdgcn_raw_buffer_load_b32(rs, static_cast<int>(off), 0, 0);
+    return __builtin_bit_cast(G, v);
+  }
+}
+
 // Per-form constants. The LDS tiles hold rows (an n index or a fiber) whose
 // k values are contiguous; every lane reads 16 bytes = KV consecutive k of
 // one row. Because the contraction is a plain sum over k, lane group
@@ -134,7 +150,10 @@ constexpr size_t mode_lds_bytes() {
 // PF: prefetch distance in k-chunks (1 or 2). With 2, two register sets
 // alternate so the global loads of chunk c+2 are in flight while chunk c
 // computes (LDS stays double buffered).
-template <int FORM, int NB, int FB, int BK, bool INNER, int PF = 1>
+// VEC: L is k-contiguous (cs = 1) and, in the lead layout, so is X; every
+// KV-element group then starts 16-byte aligned and m is a multiple of KV, so
+// each group is loaded with 16-byte loads (the host checks these conditions).
+template <int FORM, int NB, int FB, int BK, bool INNER, int PF = 1, bool VEC = false>
 __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t bx, int64_t by,
                                           char* __restrict__ lds) {
   using FT = FormT<FORM>;
@@ -221,36 +240,71 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t bx, int64_t
 
   // CHECK: the chunk reaches past k = m; those k read as zero.
   // SET: the register set the chunk is loaded into.
+  // Chunk loads go through buffer resources (base and size in scalar
+  // registers, built per chunk): each load is the fixed 32-bit per-thread
+  // offset, with no per-load address arithmetic. A k past m (CHECK, the last
+  // chunk) gets an offset beyond the resource's size, which the hardware
+  // answers with zero, so no value is ever selected after it is loaded. The
+  // host keeps each launch's operands below 2^31 bytes.
+  const uint32_t x_bytes = static_cast<uint32_t>(a.Il * a.m * a.Ir * sizeof(G));
+  const uint32_t l_bytes =
+      static_cast<uint32_t>(((n - 1) * a.rs + (m - 1) * a.cs + 1) * sizeof(G));
   auto load_chunk = [&](int64_t k0, auto check, auto set) {
     constexpr bool CHECK = decltype(check)::value;
     constexpr int SET = decltype(set)::value;
-    const char* xb = reinterpret_cast<const char*>(X + k0 * xkstep);
-    const char* lb = reinterpret_cast<const char*>(L + k0 * a.cs);
+    constexpr uint32_t kOut = 0x80000000u;  // >= any resource size here
+    const uint32_t xk = static_cast<uint32_t>(k0 * xkstep * sizeof(G));
+    const uint32_t lk = static_cast<uint32_t>(k0 * a.cs * sizeof(G));
+    const auto xrs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<char*>(reinterpret_cast<const char*>(X)) + xk, 0, x_bytes - xk, kBufferFlags);
+    const auto lrs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<char*>(reinterpret_cast<const char*>(L)) + lk, 0, l_bytes - lk, kBufferFlags);
+    // a group of KV k values as 16-byte loads (a whole group is valid or not:
+    // m is a multiple of KV)
+    auto load_group = [&](__amdgpu_buffer_rsrc_t rs, uint32_t off, G (&dst)[KV]) {
+      typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+      constexpr int NQ = KV * sizeof(G) / 16;
 #pragma unroll
-    for (int s = 0; s < XT; ++s)
+      for (int q = 0; q < NQ; ++q) {
+        const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(
+            rs, static_cast<int>(off == kOut ? kOut : off + 16 * q), 0, 0);
+        typedef G g16 __attribute__((ext_vector_type(16 / sizeof(G))));
+        const g16 gv = __builtin_bit_cast(g16, v);
 #pragma unroll
-      for (int e = 0; e < KV; ++e) {
-        if constexpr (CHECK) {
-          const bool ok = k0 + xkg[s] * KV + e < m;
-          // a k past m may lie past the tensor: read X[0] instead, then zero
-          const G v = ok ? *reinterpret_cast<const G*>(xb + xo[s][e]) : X[0];
-          xr[SET][s][e] = ok ? v : G(0);
-        } else {
-          xr[SET][s][e] = *reinterpret_cast<const G*>(xb + xo[s][e]);
+        for (int e = 0; e < static_cast<int>(16 / sizeof(G)); ++e)
+          dst[q * (16 / sizeof(G)) + e] = gv[e];
+      }
+    };
+#pragma unroll
+    for (int s = 0; s < XT; ++s) {
+      if constexpr (VEC && !INNER) {
+        uint32_t off = xo[s][0];
+        if constexpr (CHECK) off = k0 + xkg[s] * KV < m ? off : kOut;
+        load_group(xrs, off, xr[SET][s]);
+      } else {
+#pragma unroll
+        for (int e = 0; e < KV; ++e) {
+          uint32_t off = xo[s][e];
+          if constexpr (CHECK) off = k0 + xkg[s] * KV + e < m ? off : kOut;
+          xr[SET][s][e] = buffer_load<G>(xrs, off);
         }
       }
+    }
 #pragma unroll
-    for (int s = 0; s < LT; ++s)
+    for (int s = 0; s < LT; ++s) {
+      if constexpr (VEC) {
+        uint32_t off = lo_[s][0];
+        if constexpr (CHECK) off = k0 + lkg[s] * KV < m ? off : kOut;
+        load_group(lrs, off, lr[SET][s]);
+      } else {
 #pragma unroll
-      for (int e = 0; e < KV; ++e) {
-        if constexpr (CHECK) {
-          const bool ok = k0 + lkg[s] * KV + e < m;
-          const G v = ok ? *reinterpret_cast<const G*>(lb + lo_[s][e]) : L[0];
-          lr[SET][s][e] = ok ? v : G(0);
-        } else {
-          lr[SET][s][e] = *reinterpret_cast<const G*>(lb + lo_[s][e]);
+        for (int e = 0; e < KV; ++e) {
+          uint32_t off = lo_[s][e];
+          if constexpr (CHECK) off = k0 + lkg[s] * KV + e < m ? off : kOut;
+          lr[SET][s][e] = buffer_load<G>(lrs, off);
         }
       }
+    }
   };
   // Registers -> LDS; the split forms write P bf16 planes.
   auto store_rows = [&](auto& tile, int row, int kg, const G (&v)[KV]) {

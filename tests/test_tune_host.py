@@ -151,8 +151,9 @@ def test_products_report_the_chain_views(lib, L, tune, seed):
     assert got2 == views(m, n, None, backward=True)
     # the reported tile follows the table
     p0 = tune.products(T, Ls)[0]
-    tune.set_tile("f64", p0["Il"], p0["m"], p0["n"], p0["Ir"], (2, 4, 16))
-    assert tune.products(T, Ls)[0]["nb"] == 2
+    tune.set_tile("f64", p0["Il"], p0["m"], p0["n"], p0["Ir"], (2, 2, 16))
+    q0 = tune.products(T, Ls)[0]
+    assert (q0["nb"], q0["fb"], q0["bk"], q0["kind"]) == (2, 2, 16, 0)
     with pytest.raises(Exception):
         tune.products(T, Ls, which="nope")
 
