@@ -59,6 +59,18 @@ __device__ __forceinline__ G buffer_load(__amdgpu_buffer_rsrc_t rs, uint32_t off
   }
 }
 
+template <typename G>
+__device__ __forceinline__ void buffer_store(G v, __amdgpu_buffer_rsrc_t rs, uint32_t off) {
+  if constexpr (sizeof(G) == 8) {
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), rs,
+                                          static_cast<int>(off), 0, 0);
+  } else {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), rs,
+                                          static_cast<int>(off), 0, 0);
+  }
+}
+
 // Per-form constants. The LDS tiles hold rows (an n index or a fiber) whose
 // k values are contiguous; every lane reads 16 bytes = KV consecutive k of
 // one row. Because the contraction is a plain sum over k, lane group

@@ -83,6 +83,9 @@ int device_cus() {
 
 bool strip_default(int form, int64_t m, int64_t n, ModeTile* out) {
   if (m < 1 || m > max_strip(form)) return false;
+  // FP32 with m <= 16: the k-loop tile (one chunk, 16-byte loads) measured
+  // faster than the strip
+  if (form == FORM_F32 && m <= 16) return false;
   const int kp = form == FORM_BF16X3 || form == FORM_BF16X6 ? (m <= 32 ? 32 : 64)
                                                              : (m <= 16 ? 16 : (m <= 32 ? 32 : 64));
   const int nb = n <= 16 ? 1 : (n <= 32 ? 2 : 4);

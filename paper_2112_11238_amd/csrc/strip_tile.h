@@ -117,8 +117,15 @@ __device__ __forceinline__ void strip_run(const ModeArgs& a, int64_t by, int64_t
   }
 
   G xr[XT][KV];
-  // Global -> registers for fiber tile bx. Fibers past F are clamped to the
-  // last one (their outputs are never stored); k >= m reads as zero.
+  // Global -> registers for fiber tile bx, through a buffer resource over
+  // the launch's X (32-bit offsets, no per-load address arithmetic). Fibers
+  // past F are clamped to the last one (their outputs are never stored); a
+  // k at or past m gets an offset past the resource and reads as zero.
+  constexpr uint32_t kOut = 0x80000000u;  // >= any resource size here
+  const auto xrs = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<void*>(a.X), 0, static_cast<int>(a.Il * a.m * a.Ir * sizeof(G)), kBufferFlags);
+  const auto yrs = __builtin_amdgcn_make_buffer_rsrc(
+      a.Y, 0, static_cast<int>(a.Il * a.n * a.Ir * sizeof(G)), kBufferFlags);
   auto load_x = [&](int64_t bx) {
     const uint32_t f0 = static_cast<uint32_t>(bx) * BF;
 #pragma unroll
@@ -134,20 +141,25 @@ __device__ __forceinline__ void strip_run(const ModeArgs& a, int64_t by, int64_t
       }
       const uint32_t kb = xkg[s] * KV;
       if constexpr (VEC) {
-        if (kb < m) {
-          const GV v = *reinterpret_cast<const GV*>(X + base + kb);
+        typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+        typedef G g16 __attribute__((ext_vector_type(16 / sizeof(G))));
+        constexpr int NQ = KV * sizeof(G) / 16;
+        constexpr int PER = 16 / sizeof(G);
+        const uint32_t off = kb < m ? (base + kb) * sizeof(G) : kOut;
 #pragma unroll
-          for (int e = 0; e < KV; ++e) xr[s][e] = v[e];
-        } else {
+        for (int q = 0; q < NQ; ++q) {
+          const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(
+              xrs, static_cast<int>(off == kOut ? kOut : off + 16 * q), 0, 0);
+          const g16 gv = __builtin_bit_cast(g16, v);
 #pragma unroll
-          for (int e = 0; e < KV; ++e) xr[s][e] = G(0);
+          for (int e = 0; e < PER; ++e) xr[s][q * PER + e] = gv[e];
         }
       } else {
         const uint32_t ks = INNER ? Il : 1;
 #pragma unroll
         for (int e = 0; e < KV; ++e) {
           const uint32_t k = kb + e;
-          xr[s][e] = k < m ? X[base + k * ks] : G(0);
+          xr[s][e] = buffer_load<G>(xrs, k < m ? (base + k * ks) * sizeof(G) : kOut);
         }
       }
     }
@@ -220,38 +232,32 @@ __device__ __forceinline__ void strip_run(const ModeArgs& a, int64_t by, int64_t
         }
       }
     }
-    // outputs of this tile (MFMA column = memory-contiguous index)
-    const uint32_t f0 = static_cast<uint32_t>(bx) * BF;
+    // outputs of this tile (MFMA column = memory-contiguous index), through a
+    // buffer resource over Y: rows past n and fibers past F get an offset
+    // past the resource and the hardware drops the store
 #pragma unroll
     for (int q = 0; q < QB; ++q)
 #pragma unroll
       for (int p = 0; p < PB; ++p) {
         acc_t val = hi[q][p];
         if constexpr (SPLIT) val = hi[q][p] + lo[q][p];
-        if constexpr (INNER) {
-          const uint32_t r = f0 + w * 16 * FB + p * 16 + c;
-          if (r >= F) continue;
-          const uint32_t b = r / Il;
-          G* yb = Y + ((r - b * Il) + Il * n * b);
+        const uint32_t f0 = static_cast<uint32_t>(bx) * BF;
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
+        for (int v = 0; v < 4; ++v) {
+          uint32_t off;
+          if constexpr (INNER) {
+            const uint32_t r = f0 + w * 16 * FB + p * 16 + c;
             const uint32_t i = i0 + q * 16 + FT::row(lane, v);
-            if (i < n) {
-              G* dst = yb + Il * i;
-              *dst = a.accumulate ? *dst + val[v] : val[v];
-            }
-          }
-        } else {
-          const uint32_t i = i0 + p * 16 + c;
-          if (i >= n) continue;
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
+            const uint32_t b = r / Il;
+            off = (r < F && i < n) ? ((r - b * Il) + Il * n * b + Il * i) * sizeof(G) : kOut;
+          } else {
+            const uint32_t i = i0 + p * 16 + c;
             const uint32_t f = f0 + w * 16 * FB + q * 16 + FT::row(lane, v);
-            if (f < F) {
-              G* dst = Y + (i + n * f);
-              *dst = a.accumulate ? *dst + val[v] : val[v];
-            }
+            off = (f < F && i < n) ? (i + n * f) * sizeof(G) : kOut;
           }
+          G y = val[v];
+          if (a.accumulate) y += buffer_load<G>(yrs, off);
+          buffer_store<G>(y, yrs, off);
         }
       }
     if (nx < ntiles) store_x(buf ^ 1);
