@@ -14,6 +14,7 @@
 #pragma once
 
 #include "gram_tile.h"
+#include "mode_tile.h"
 
 namespace kp {
 namespace gram {
@@ -53,8 +54,6 @@ __device__ __forceinline__ void gram_strip(const GramArgs& g, int64_t c_begin, i
   QTile* sQ = reinterpret_cast<QTile*>(lds);
   PTile* sP = reinterpret_cast<PTile*>(lds + 2 * sizeof(QTile));
 
-  const E* __restrict__ Q = static_cast<const E*>(g.Q);
-  const E* __restrict__ P = static_cast<const E*>(g.P);
   // 32-bit index math: the host keeps each operand below 2^31 bytes
   const uint32_t Il = static_cast<uint32_t>(g.Il), n = static_cast<uint32_t>(g.n);
   const uint32_t m = static_cast<uint32_t>(g.m);
@@ -66,29 +65,37 @@ __device__ __forceinline__ void gram_strip(const GramArgs& g, int64_t c_begin, i
   const int gq = lane >> 4;
 
   E qv[NQ][KV], pv[NP][KV];
-  // offset of element (fiber r, row i) of a view with `len` rows
-  auto offset = [&](uint32_t r, uint32_t i, uint32_t len) -> uint32_t {
-    if constexpr (INNER) {
-      const uint32_t b = r / Il;
-      return (r - b * Il) + Il * (i + len * b);
-    } else {
-      return i + len * r;
-    }
-  };
+  // loads through buffer resources over Q and P (32-bit offsets); elements
+  // past F, n or m get an offset past the resource and read as zero
+  constexpr uint32_t kOut = 0x80000000u;
+  const auto qrs = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<void*>(g.Q), 0, static_cast<int>(g.Il * g.n * g.Ir * sizeof(E)),
+      tile::kBufferFlags);
+  const auto prs = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<void*>(g.P), 0, static_cast<int>(g.Il * g.m * g.Ir * sizeof(E)),
+      tile::kBufferFlags);
   auto load = [&](int64_t ch) {
     const uint32_t r0 = static_cast<uint32_t>(ch) * BR;
+    // INNER: one fiber per task (its base offset computed once, rows at
+    // stride Il); lead: one row per task, fibers at stride len
 #pragma unroll
     for (int s = 0; s < NQ; ++s) {
       const int id = t + s * kThreads;
       const int fr = INNER ? id % BR : (id / RQ) * KV;   // first fiber of the task
       const int row = INNER ? (id / BR) * KV : id % RQ;  // first row of the task
+      uint32_t base = 0;
+      if constexpr (INNER) {
+        const uint32_t r = r0 + fr;
+        const uint32_t b = r / Il;
+        base = (r - b * Il) + Il * n * b;
+      }
 #pragma unroll
       for (int e = 0; e < KV; ++e) {
         const uint32_t r = r0 + fr + (INNER ? 0 : e);
         const uint32_t i = row + (INNER ? e : 0);
         const bool ok = id < TQ && r < F && i < n;
-        const E v = Q[ok ? offset(r, i, n) : 0];
-        qv[s][e] = ok ? v : E(0);
+        const uint32_t off = INNER ? base + Il * i : i + n * r;
+        qv[s][e] = tile::buffer_load<E>(qrs, ok ? off * sizeof(E) : kOut);
       }
     }
 #pragma unroll
@@ -96,13 +103,19 @@ __device__ __forceinline__ void gram_strip(const GramArgs& g, int64_t c_begin, i
       const int id = t + s * kThreads;
       const int fr = INNER ? id % BR : (id / RP) * KV;
       const int row = INNER ? (id / BR) * KV : id % RP;
+      uint32_t base = 0;
+      if constexpr (INNER) {
+        const uint32_t r = r0 + fr;
+        const uint32_t b = r / Il;
+        base = (r - b * Il) + Il * m * b;
+      }
 #pragma unroll
       for (int e = 0; e < KV; ++e) {
         const uint32_t r = r0 + fr + (INNER ? 0 : e);
         const uint32_t j = row + (INNER ? e : 0);
         const bool ok = id < TP && r < F && j < m;
-        const E v = P[ok ? offset(r, j, m) : 0];
-        pv[s][e] = ok ? v : E(0);
+        const uint32_t off = INNER ? base + Il * j : j + m * r;
+        pv[s][e] = tile::buffer_load<E>(prs, ok ? off * sizeof(E) : kOut);
       }
     }
   };

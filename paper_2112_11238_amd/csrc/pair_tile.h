@@ -86,8 +86,6 @@ __device__ __forceinline__ void pair_run(const PairArgs& a, int64_t t0, int64_t 
   XTl& sX = *reinterpret_cast<XTl*>(lds + LY::l1 + LY::l2);
   ZTl& sZ = *reinterpret_cast<ZTl*>(lds + LY::l1 + LY::l2 + LY::x);
 
-  const G* __restrict__ X = static_cast<const G*>(a.X);
-  G* __restrict__ Y = static_cast<G*>(a.Y);
   const G* __restrict__ L1 = static_cast<const G*>(a.L1);
   const G* __restrict__ L2 = static_cast<const G*>(a.L2);
   // 32-bit index math: the host keeps every launch below 2^31 bytes
@@ -145,8 +143,16 @@ __device__ __forceinline__ void pair_run(const PairArgs& a, int64_t t0, int64_t 
   }
 
   G xr[XT][KV];
-  // X tile -> registers: task = (fiber f, j1 group kg, j2); k past m reads 0,
-  // fibers past F are clamped (their outputs are never stored)
+  // X tile -> registers through a buffer resource (32-bit offsets): task =
+  // (fiber f, j1 group kg, j2); a j1 or j2 past m1, m2 gets an offset past the
+  // resource and reads as zero; fibers past F are clamped (their outputs are
+  // never stored). Y is written through a resource too.
+  constexpr uint32_t kOut = 0x80000000u;
+  const auto xrs = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<void*>(a.X), 0, static_cast<int>(a.Il * a.m1 * a.m2 * a.Ir * sizeof(G)),
+      kBufferFlags);
+  const auto yrs = __builtin_amdgcn_make_buffer_rsrc(
+      a.Y, 0, static_cast<int>(a.Il * a.n1 * a.n2 * a.Ir * sizeof(G)), kBufferFlags);
   auto load_x = [&](int64_t bx) {
     const uint32_t f0 = static_cast<uint32_t>(bx) * BF;
 #pragma unroll
@@ -162,7 +168,8 @@ __device__ __forceinline__ void pair_run(const PairArgs& a, int64_t t0, int64_t 
 #pragma unroll
       for (int e = 0; e < KV; ++e) {
         const uint32_t j1 = kg * KV + e;
-        xr[s][e] = (id < XTASKS && j1 < m1 && j2 < m2) ? X[base + Il * j1] : G(0);
+        xr[s][e] = buffer_load<G>(
+            xrs, (id < XTASKS && j1 < m1 && j2 < m2) ? (base + Il * j1) * sizeof(G) : kOut);
       }
     }
   };
@@ -259,16 +266,15 @@ __device__ __forceinline__ void pair_run(const PairArgs& a, int64_t t0, int64_t 
           macro_step<FORM>(la, zb, hi[q], lo[q]);
         }
       }
-      if (r < F) {
 #pragma unroll
-        for (int q = 0; q < NB2; ++q) {
-          acc_t val = hi[q];
-          if constexpr (SPLIT) val = hi[q] + lo[q];
+      for (int q = 0; q < NB2; ++q) {
+        acc_t val = hi[q];
+        if constexpr (SPLIT) val = hi[q] + lo[q];
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const uint32_t i2 = q * 16 + FT::row(lane, v);
-            if (i2 < n2) Y[ybase + Il * (i1 + n1 * i2)] = val[v];
-          }
+        for (int v = 0; v < 4; ++v) {
+          const uint32_t i2 = q * 16 + FT::row(lane, v);
+          buffer_store<G>(val[v], yrs,
+                          (r < F && i2 < n2) ? (ybase + Il * (i1 + n1 * i2)) * sizeof(G) : kOut);
         }
       }
     }

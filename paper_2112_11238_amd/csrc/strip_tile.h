@@ -46,16 +46,13 @@ __device__ __forceinline__ void strip_run(const ModeArgs& a, int64_t by, int64_t
   static_assert(KP % MK == 0, "KP must be a multiple of the macro step");
   static_assert(!INNER || kThreads % BF == 0, "BF must divide the block size");
   static_assert(!(INNER && VEC), "vector loads are for the lead layout");
-  typedef G GV __attribute__((ext_vector_type(KV)));
 
   typedef SE LTile[P][BN][LDK];
   typedef SE XTile[P][BF][LDK];
   LTile& sL = *reinterpret_cast<LTile*>(lds);
   XTile* sX = reinterpret_cast<XTile*>(lds + sizeof(LTile));
 
-  const G* __restrict__ X = static_cast<const G*>(a.X);
   const G* __restrict__ L = static_cast<const G*>(a.L);
-  G* __restrict__ Y = static_cast<G*>(a.Y);
   // 32-bit index math: the host keeps every launch below 2^31 bytes
   const uint32_t Il = static_cast<uint32_t>(a.Il), m = static_cast<uint32_t>(a.m);
   const uint32_t n = static_cast<uint32_t>(a.n);
