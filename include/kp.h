@@ -93,7 +93,9 @@ typedef struct {
   void* data;    /* device pointer */
 } kp_tensor;
 
-/* rows x cols matrix, element (i,j) at data[i*rs + j*cs] (elements, not bytes). */
+/* rows x cols matrix, element (i,j) at data[i*rs + j*cs] (elements, not bytes).
+ * rs, cs >= 0 (a negative stride is KP_ERR_VALUE); the span the strides
+ * address must stay below 2^31 bytes (KP_ERR_SHAPE otherwise). */
 typedef struct {
   int64_t rows, cols;
   int64_t rs, cs;

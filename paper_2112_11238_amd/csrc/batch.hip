@@ -398,6 +398,10 @@ int check_item(const kp_batch_item& it, int prec, bool* has_bwd) {
     if (!L.data) return KP_ERR_NULL;
     if (L.dtype != T.dtype) return KP_ERR_DTYPE;
     if (L.cols != T.dims[k] || L.rows < 1 || it.S.dims[k] != L.rows) return KP_ERR_SHAPE;
+    if (L.rs < 0 || L.cs < 0) return KP_ERR_VALUE;
+    if (((L.rows - 1) * L.rs + (L.cols - 1) * L.cs + 1) * static_cast<int64_t>(es) >=
+        (static_cast<int64_t>(1) << 31))
+      return KP_ERR_SHAPE;
   }
   // every intermediate must fit the 32-bit offsets of the tile code
   int64_t cur = numel_t(T);
@@ -421,6 +425,7 @@ int check_item(const kp_batch_item& it, int prec, bool* has_bwd) {
       if (!D.data) continue;
       if (D.dtype != T.dtype || D.rows != it.L[k].rows || D.cols != it.L[k].cols)
         return KP_ERR_SHAPE;
+      if (D.rs < 0 || D.cs < 0) return KP_ERR_VALUE;
     }
   }
   return KP_OK;

@@ -40,8 +40,14 @@ int check_tensor(const kp_tensor* t, bool need_data) {
 
 int check_matrix(const kp_matrix* L, int dtype) {
   if (L->rows < 0 || L->cols < 0) return KP_ERR_SHAPE;
+  if (L->rs < 0 || L->cs < 0) return KP_ERR_VALUE;
   if (L->dtype != dtype) return KP_ERR_DTYPE;
   if (!L->data && L->rows > 0 && L->cols > 0) return KP_ERR_NULL;
+  // the kernels address factors with 32-bit byte offsets
+  if (L->rows > 0 && L->cols > 0 &&
+      ((L->rows - 1) * L->rs + (L->cols - 1) * L->cs + 1) * static_cast<int64_t>(elem_size(dtype)) >=
+          (static_cast<int64_t>(1) << 31))
+    return KP_ERR_SHAPE;
   return KP_OK;
 }
 

@@ -148,6 +148,15 @@ def test_mump_argument_errors(lib, L):
     # NULL data with a non-empty tensor
     assert call(ctypes.byref(tensor(L, [4, 5, 6], data=None)), ctypes.byref(M), 2,
                 ctypes.byref(S)) == -1
+    # negative factor strides; a factor spanning 2^31 bytes or more
+    Mneg = matrix(L, 7, 5)
+    Mneg.rs = -5
+    assert call(ctypes.byref(T), ctypes.byref(Mneg), 2, ctypes.byref(S)) == -9
+    Mneg.rs, Mneg.cs = 5, -1
+    assert call(ctypes.byref(T), ctypes.byref(Mneg), 2, ctypes.byref(S)) == -9
+    Mbig = matrix(L, 7, 5)
+    Mbig.rs = 1 << 26   # 6 * 2^26 * 8 bytes > 2^31
+    assert call(ctypes.byref(T), ctypes.byref(Mbig), 2, ctypes.byref(S)) == -4
 
 
 @no_device

@@ -225,5 +225,9 @@ def test_plan_rejects_bad_items(lib, L):
     assert lib.kp_batch_plan(1, items, 6, FAKE_WS, ws, big, pb) == 0   # FP32 + BF16x6 ok
     items64 = make_items(L, [((3, 4), (5, 6))], 0, False, alloc)
     assert lib.kp_batch_workspace(1, items64, 3) == 0                   # BF16 needs FP32
+    neg = make_items(L, [((3, 4), (5, 6))], 1, False, alloc)
+    neg[0].L[1].cs = -1                                                 # negative stride
+    assert lib.kp_batch_workspace(1, neg, 0) == 0
+    assert lib.kp_batch_plan(1, neg, 0, FAKE_WS, ws, big, pb) == -9
     assert lib.kp_batch_info(big, None, None, None) == 0
     assert lib.kp_batch_info(buf, None, None, None) == -9   # not a plan
