@@ -114,6 +114,16 @@ typedef struct {
 int kp_mump(const kp_tensor* T, const kp_matrix* L, int mu, kp_tensor* S,
             int prec, int accumulate, hipStream_t stream);
 
+/* ---- Kronecker-sum action (Sec. 2, the action of a Kronecker sum) ----------
+ * S = T x_1 A_1 + T x_2 A_2 + ... + T x_d A_d, that is
+ * vec(S) = (A_d (+) ... (+) A_1) vec(T): d mu-mode products on `stream`, the
+ * first writing S, each later one adding to it. Every A_mu is m_mu x m_mu
+ * (none may be NULL); S has the sizes of T and must not overlap T or any A.
+ * prec as for kp_mump. Errors: as kp_mump, KP_ERR_NULL for a NULL A_mu,
+ * KP_ERR_SHAPE for a non-square A_mu or mismatched S. */
+int kp_kronsum(const kp_tensor* T, const kp_matrix* const A[], kp_tensor* S, int prec,
+               hipStream_t stream);
+
 /* ---- Tucker operator (Sec. 2, Definition of the Tucker operator) --------------
  * S = T x_1 L[0] x_2 L[1] ... x_d L[d-1]. L[k] is n_k x m_k; S has dims
  * n_1..n_d. A NULL L[k] is the identity (mode skipped, n_k = m_k).

@@ -6,8 +6,8 @@ hand-written HIP kernels behind the C-ABI of include/kp.h (libkp.so), with a
 thin torch binding (ops) that only marshals arguments.
 """
 from .ops import (mump, tucker, tucker_with_cache, tucker_backward,  # noqa: F401
-                  tucker_autograd, TuckerFunction, expm, BatchedTucker, force_tile)
+                  tucker_autograd, TuckerFunction, expm, BatchedTucker, force_tile, kronsum)
 from . import tune  # noqa: F401,E402
 
 __all__ = ["mump", "tucker", "tucker_with_cache", "tucker_backward", "tucker_autograd",
-           "TuckerFunction", "expm", "BatchedTucker", "force_tile", "tune"]
+           "TuckerFunction", "expm", "BatchedTucker", "force_tile", "kronsum", "tune"]

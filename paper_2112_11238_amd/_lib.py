@@ -69,6 +69,7 @@ _MA = P(P(KpMatrix))
 # name -> (restype, argtypes); mirrors include/kp.h
 SIGNATURES = {
     "kp_mump": (ctypes.c_int, [_T, _M, ctypes.c_int, _T, ctypes.c_int, ctypes.c_int, _V]),
+    "kp_kronsum": (ctypes.c_int, [_T, _MA, _T, ctypes.c_int, _V]),
     "kp_tucker_workspace": (_S, [_T, _MA, ctypes.c_int]),
     "kp_tucker_cache_size": (_S, [_T, _MA]),
     "kp_tucker_order": (ctypes.c_int, [_T, _MA, P(ctypes.c_int), P(ctypes.c_int)]),

@@ -331,6 +331,41 @@ int kp_mump(const kp_tensor* T, const kp_matrix* L, int mu, kp_tensor* S, int pr
   return hip_status(launch_mode(form_of(prec, T->dtype), a, tile_override(), stream));
 }
 
+int kp_kronsum(const kp_tensor* T, const kp_matrix* const* A, kp_tensor* S, int prec,
+               hipStream_t stream) {
+  int st = check_tensor(T, true);
+  if (st) return st;
+  if (!A || !S) return KP_ERR_NULL;
+  st = check_tensor(S, true);
+  if (st) return st;
+  const int d = T->d;
+  for (int k = 0; k < d; ++k) {
+    if (!A[k]) return KP_ERR_NULL;
+    st = check_matrix(A[k], T->dtype);
+    if (st) return st;
+    if (A[k]->rows != T->dims[k] || A[k]->cols != T->dims[k]) return KP_ERR_SHAPE;
+  }
+  st = check_prec(prec, T->dtype);
+  if (st) return st;
+  if (S->dtype != T->dtype) return KP_ERR_DTYPE;
+  if (S->d != d) return KP_ERR_SHAPE;
+  for (int k = 0; k < d; ++k)
+    if (S->dims[k] != T->dims[k]) return KP_ERR_SHAPE;
+  const size_t es = elem_size(T->dtype);
+  const size_t sb = static_cast<size_t>(numel(*S)) * es;
+  if (overlaps(S->data, sb, T->data, sb)) return KP_ERR_ALIAS;
+  for (int k = 0; k < d; ++k)
+    if (overlaps(S->data, sb, A[k]->data, matrix_span_bytes(*A[k]))) return KP_ERR_ALIAS;
+  if (numel(*S) == 0) return KP_OK;
+  const int form = form_of(prec, T->dtype);
+  for (int k = 0; k < d; ++k) {
+    const ModeArgs a = mode_args(T->data, S->data, T->dims, d, k, *A[k], k > 0 ? 1 : 0);
+    st = hip_status(launch_mode(form, a, tile_override(), stream));
+    if (st) return st;
+  }
+  return KP_OK;
+}
+
 size_t kp_tucker_workspace(const kp_tensor* T, const kp_matrix* const* L, int prec) {
   if (validate_tucker_args(T, L, prec)) return 0;
   // exactly what kp_tucker checks on its workspace path (no cache)

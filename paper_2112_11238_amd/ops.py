@@ -120,6 +120,25 @@ def mump(T, L, mu, prec="native", out=None, accumulate=False):
     return out
 
 
+def kronsum(T, As, prec="native", out=None):
+    """S = T x_1 A_1 + ... + T x_d A_d: the action of the Kronecker sum of the
+    square A_mu on vec(T) (kp_kronsum)."""
+    _check_device(T, *As)
+    d = T.dim()
+    if len(As) != d:
+        raise ValueError(f"need {d} matrices, got {len(As)}")
+    Tc = _canon(T)
+    if out is None:
+        out = torch.empty_like(Tc)
+    elif list(out.shape) != list(T.shape) or not out.is_contiguous():
+        raise ValueError("output must be a contiguous tensor of T's shape")
+    td, sd = _tdesc(Tc, True), _tdesc(out, True)
+    arr = _mlist([_mdesc(A) for A in As][::-1])
+    check(lib().kp_kronsum(ctypes.byref(td), arr, ctypes.byref(sd), _prec(prec), _stream()),
+          "kp_kronsum")
+    return out
+
+
 def _tucker_call(T, Ls, prec, want_cache):
     _check_device(T, *Ls)
     d = T.dim()

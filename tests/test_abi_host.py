@@ -160,6 +160,21 @@ def test_mump_argument_errors(lib, L):
 
 
 @no_device
+def test_kronsum_argument_errors(lib, L):
+    T = tensor(L, [4, 5, 6])
+    S = tensor(L, [4, 5, 6], data=FAKE + 0x200000)
+    As = [matrix(L, k, k, data=FAKE + 0x400000 + 0x1000 * j) for j, k in enumerate([4, 5, 6])]
+    call = lambda t, arr, s, prec=0: lib.kp_kronsum(t, arr, s, prec, None)
+    assert call(None, mlist(L, As), ctypes.byref(S)) == -1
+    assert call(ctypes.byref(T), mlist(L, [As[0], None, As[2]]), ctypes.byref(S)) == -1
+    assert call(ctypes.byref(T), mlist(L, [As[0], matrix(L, 5, 4), As[2]]),
+                ctypes.byref(S)) == -4                                  # not square / wrong size
+    assert call(ctypes.byref(T), mlist(L, As), ctypes.byref(tensor(L, [4, 5, 7]))) == -4
+    assert call(ctypes.byref(T), mlist(L, As), ctypes.byref(S), prec=3) == -5
+    assert call(ctypes.byref(T), mlist(L, As), ctypes.byref(tensor(L, [4, 5, 6], data=FAKE))) == -6
+
+
+@no_device
 def test_tucker_argument_errors(lib, L):
     T = tensor(L, [4, 5, 6], dtype=1)
     Ms = [matrix(L, 3, 4, 1), matrix(L, 2, 5, 1), matrix(L, 5, 6, 1)]
