@@ -16,6 +16,9 @@ approach for multidimensional tensor-structured problems"):
                   the exponential of the Dirichlet finite-difference Laplacian
                   (closed form), barycentric Lagrange matrices on Chebyshev
                   nodes, the 5-D Runge function.
+* ``semilinear`` -- the semilinear diffusion-reaction experiment: tridiagonal
+                  inverses (ADI factors), preconditioned conjugate gradients on
+                  the Kronecker-sum matrix, backward-forward Euler steps.
 * ``grad``     -- the gradient of a scalar loss through the Tucker operator
                   and a central finite-difference checker.
 
@@ -29,6 +32,9 @@ from .factors import (fd_laplacian_dirichlet, expm_fd_laplacian_dirichlet,
                       dst1_eigenpairs, chebyshev_nodes, chebyshev_weights,
                       lagrange_matrix, runge)
 from .grad import tucker_vjp, central_fd_directional
+from .semilinear import (tridiag, tridiag_inverse, pcg, semilinear_grid, semilinear_u0,
+                         semilinear_laplacian_u0, semilinear_phi, semilinear_rhs,
+                         semilinear_factors, semilinear_imex)
 
 __all__ = [
     "vec", "unvec", "mumat", "mump", "tucker", "nested", "tucker_entry",
@@ -36,4 +42,7 @@ __all__ = [
     "fd_laplacian_dirichlet", "expm_fd_laplacian_dirichlet", "dst1_eigenpairs",
     "chebyshev_nodes", "chebyshev_weights", "lagrange_matrix", "runge",
     "tucker_vjp", "central_fd_directional",
+    "tridiag", "tridiag_inverse", "pcg", "semilinear_grid", "semilinear_u0",
+    "semilinear_laplacian_u0", "semilinear_phi", "semilinear_rhs", "semilinear_factors",
+    "semilinear_imex",
 ]
