@@ -222,6 +222,76 @@ size_t kp_expm_workspace(int64_t n, int64_t count);
 int kp_expm_f64(const double* A, int64_t n, int64_t count, double tau, double* E, void* ws,
                 size_t ws_bytes, hipStream_t stream);
 
+/* ---- inverse of tridiagonal matrices in FP64 (Sec. 3.4, ADI factors) --------
+ * E_k = (shift I + scale T_k)^{-1} for `count` tridiagonal n x n matrices T_k
+ * given by their diagonals in device memory (n doubles each, matrix k at
+ * offset k*n): T[i][i-1] = lower[i] (i >= 1), T[i][i] = diag[i],
+ * T[i][i+1] = upper[i] (i <= n-2); lower[0] and upper[n-1] are not read.
+ * E receives `count` column-major n x n matrices one after another. With
+ * shift = 1, scale = -tau and T the second difference A_mu this is the
+ * factor (I - tau A_mu)^{-1} of the ADI-type preconditioner.
+ * Gaussian elimination without pivoting per column of the identity: the
+ * matrix must be one for which that is stable (diagonally dominant, or
+ * symmetric positive definite, as I - tau A_mu is); a zero pivot propagates
+ * Inf/NaN. n <= 2048, count <= 65535. No workspace; never synchronises.
+ * Errors: KP_ERR_SHAPE (n or count out of range), KP_ERR_NULL, KP_ERR_VALUE
+ * (shift or scale not finite), KP_ERR_ALIAS (E overlaps a diagonal). */
+int kp_tridiag_inverse_f64(const double* lower, const double* diag, const double* upper,
+                           int64_t n, int64_t count, double shift, double scale, double* E,
+                           hipStream_t stream);
+
+/* ---- preconditioned conjugate gradients on a Kronecker sum (Sec. 3.4) -------
+ * Solves (M_d (+) ... (+) M_1) vec(X) = vec(B) for symmetric positive definite
+ * systems, FP64. The matrix action is the Kronecker-sum action (kp_kronsum)
+ * with the square M[k] (m_k x m_k, none NULL). If P is non-NULL the
+ * preconditioner action is the Tucker operator R x_1 P[0] ... x_d P[d-1]
+ * (kp_tucker; a NULL P[k] is the identity), i.e. P[k] holds the inverse of
+ * the k-th factor of a Kronecker-product preconditioner; P == NULL runs plain
+ * conjugate gradients.
+ * X holds the initial guess on entry and the solution on return. Iterations
+ * stop when ||B - M X||_2 <= tol ||B||_2 (also before the first) or after
+ * maxit; B == 0 returns X = 0. *iters and *relres (each may be NULL) receive
+ * the iteration count and the final relative residual; not converging within
+ * maxit is not an error (relres > tol tells).
+ * The iteration loop runs on the host and waits for `stream` once per
+ * iteration to read the residual norm, so this call blocks and cannot be
+ * captured into a graph. ws_bytes >= kp_pcg_workspace(X, P).
+ * Errors: KP_ERR_NULL, KP_ERR_ORDER, KP_ERR_DTYPE (not FP64), KP_ERR_SHAPE
+ * (B, X, M[k], P[k] sizes), KP_ERR_VALUE (tol negative or not finite,
+ * maxit < 0, a negative stride), KP_ERR_WORKSPACE, KP_ERR_ALIAS (X overlaps B,
+ * a factor or ws; B or a factor overlaps ws). */
+size_t kp_pcg_workspace(const kp_tensor* X, const kp_matrix* const* P);
+int kp_pcg_kronsum(const kp_tensor* B, const kp_matrix* const* M, const kp_matrix* const* P,
+                   kp_tensor* X, double tol, int maxit, void* ws, size_t ws_bytes, int* iters,
+                   double* relres, hipStream_t stream);
+
+/* ---- backward-forward Euler for the semilinear experiment (Sec. 4.5) -------
+ * u_t = Laplacian(u) + 1/(1 + u^2) + Phi(t, x) on the interior grid points
+ * x_mu = (i_mu + 1) h[mu] of [0,1]^d (column-major U, dims m_1..m_d), with
+ * Phi(t, x) = e^t (u0 - Laplacian(u0)) - 1/(1 + e^{2t} u0^2) and
+ * u0 = prod_mu x_mu (1 - x_mu), so that e^t u0 solves the problem.
+ * The discrete Laplacian is the Kronecker sum of the tridiagonal A_mu given
+ * by the device diagonals lower[mu], diag[mu], upper[mu] (m_mu doubles each,
+ * layout as kp_tridiag_inverse_f64). Each of `steps` steps, from t0 on with
+ * step tau, solves
+ *   (M_d (+) ... (+) M_1) u_{k+1} = u_k + tau (1/(1 + u_k^2) + Phi(t_k)),
+ *   M_mu = I/d - tau A_mu,
+ * by kp_pcg_kronsum from u_k (relative tolerance tol, at most maxit
+ * iterations), with the ADI preconditioner factors (I - tau A_mu)^{-1}
+ * (built on the device) if `precondition` is non-zero. U is updated in
+ * place; iters (host, `steps` ints, may be NULL) receives the iterations of
+ * each step. Blocks like kp_pcg_kronsum. m_mu <= 2048.
+ * ws_bytes >= kp_semilinear_workspace(d, dims).
+ * Errors: KP_ERR_NULL, KP_ERR_ORDER, KP_ERR_DTYPE (U not FP64), KP_ERR_SHAPE,
+ * KP_ERR_VALUE (h not positive, t0 / tau / tol not finite, steps, maxit or
+ * tol negative), KP_ERR_WORKSPACE, KP_ERR_ALIAS (U overlaps ws or a
+ * diagonal). */
+size_t kp_semilinear_workspace(int d, const int64_t* dims);
+int kp_semilinear_imex_f64(kp_tensor* U, const double* const* lower, const double* const* diag,
+                           const double* const* upper, const double* h, double t0, double tau,
+                           int steps, double tol, int maxit, int precondition, void* ws,
+                           size_t ws_bytes, int* iters, hipStream_t stream);
+
 /* ---- tuning ----------------------------------------------------------------
  * A tile is (nb, fb, bk, occ, pf, kind):
  *   kind 0  k-loop tile: nb 16-wide blocks along n per workgroup, fb 16-wide

@@ -24,6 +24,10 @@ Table 1 and Sec. 4.1; its applications supply structured factors):
                 points of [-1, 1] (Sec. 4.3 shape, with d=6).
 * ``batch64``   64 tensors of order 4, each mode size uniform in [16, 64],
                 square factors with entries N(0,1)/sqrt(n_mu).
+* ``semilinear`` the semilinear diffusion-reaction experiment (Sec. 4.5):
+                grids of n = (40, 44, 48) interior points, the diagonals of
+                each second difference, the initial value
+                prod_mu x_mu (1 - x_mu), tau = 0.01, 100 steps to t = 1.
 """
 from __future__ import annotations
 
@@ -75,6 +79,37 @@ def heat_matrix(n=128):
     h = 1.0 / (n + 1)
     A = -2.0 * np.eye(n) + np.eye(n, k=1) + np.eye(n, k=-1)
     return A / (h * h)
+
+
+def second_difference_diagonals(n):
+    """(lower, diag, upper, h) of tridiag(1, -2, 1)/h^2 on n interior points,
+    h = 1/(n+1) (lower[0] and upper[n-1] are padding)."""
+    h = 1.0 / (n + 1)
+    off = np.full(n, 1.0 / (h * h))
+    return off, np.full(n, -2.0 / (h * h)), off.copy(), h
+
+
+def semilinear(ns=(40, 44, 48), tau=0.01, steps=100):
+    """Returns (u0, [(lower, diag, upper, h) per axis], tau, steps): the
+    initial value prod_mu x_mu (1 - x_mu) on the interior grid x = i h,
+    i = 1..n_mu (axis mu-1 = x_mu), and each axis's second difference."""
+    diags = [second_difference_diagonals(n) for n in ns]
+    u0 = np.ones(())
+    for n, (_, _, _, h) in zip(ns, diags):
+        x = np.arange(1, n + 1) * h
+        u0 = np.multiply.outer(u0, x * (1.0 - x))
+    return u0, diags, tau, steps
+
+
+def spd_matrices(seed, ns, shift=1.0):
+    """Symmetric positive definite matrices B B^T / n + shift I, B standard
+    normal n x n, one per size in ns (drawn in order)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for n in ns:
+        B = _normal(rng, (n, n))
+        out.append(B @ B.T / n + shift * np.eye(n))
+    return out
 
 
 def heat128(seed=SEED, n=128, d=3, tau=1e-3):

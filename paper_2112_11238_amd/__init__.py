@@ -6,8 +6,10 @@ hand-written HIP kernels behind the C-ABI of include/kp.h (libkp.so), with a
 thin torch binding (ops) that only marshals arguments.
 """
 from .ops import (mump, tucker, tucker_with_cache, tucker_backward,  # noqa: F401
-                  tucker_autograd, TuckerFunction, expm, BatchedTucker, force_tile, kronsum)
+                  tucker_autograd, TuckerFunction, expm, BatchedTucker, force_tile, kronsum,
+                  tridiag_inverse, pcg_kronsum, semilinear_imex)
 from . import tune  # noqa: F401,E402
 
 __all__ = ["mump", "tucker", "tucker_with_cache", "tucker_backward", "tucker_autograd",
-           "TuckerFunction", "expm", "BatchedTucker", "force_tile", "kronsum", "tune"]
+           "TuckerFunction", "expm", "BatchedTucker", "force_tile", "kronsum",
+           "tridiag_inverse", "pcg_kronsum", "semilinear_imex", "tune"]

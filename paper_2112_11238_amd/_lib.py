@@ -80,6 +80,16 @@ SIGNATURES = {
     "kp_expm_workspace": (_S, [ctypes.c_int64, ctypes.c_int64]),
     "kp_expm_f64": (ctypes.c_int, [_V, ctypes.c_int64, ctypes.c_int64, ctypes.c_double, _V, _V,
                                    _S, _V]),
+    "kp_tridiag_inverse_f64": (ctypes.c_int, [_V, _V, _V, ctypes.c_int64, ctypes.c_int64,
+                                              ctypes.c_double, ctypes.c_double, _V, _V]),
+    "kp_pcg_workspace": (_S, [_T, _MA]),
+    "kp_pcg_kronsum": (ctypes.c_int, [_T, _MA, _MA, _T, ctypes.c_double, ctypes.c_int, _V, _S,
+                                      P(ctypes.c_int), P(ctypes.c_double), _V]),
+    "kp_semilinear_workspace": (_S, [ctypes.c_int, P(ctypes.c_int64)]),
+    "kp_semilinear_imex_f64": (ctypes.c_int, [_T, P(_V), P(_V), P(_V), P(ctypes.c_double),
+                                              ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                              ctypes.c_double, ctypes.c_int, ctypes.c_int, _V, _S,
+                                              P(ctypes.c_int), _V]),
     "kp_batch_workspace": (_S, [ctypes.c_int, P(KpBatchItem), ctypes.c_int]),
     "kp_batch_plan_bytes": (_S, [ctypes.c_int, P(KpBatchItem), ctypes.c_int]),
     "kp_batch_plan": (ctypes.c_int, [ctypes.c_int, P(KpBatchItem), ctypes.c_int, _V, _S, _V, _S]),

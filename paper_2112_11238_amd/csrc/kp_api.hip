@@ -169,8 +169,6 @@ void make_chain(const kp_tensor& T, const kp_matrix* const* L, bool definition_o
   }
 }
 
-// Workspace for a chain: two ping-pong buffers for the intermediates
-// (steps 1..count-1), buffer (s-1)&1 for the output of step s-1.
 // Workspace for a chain: two ping-pong buffers, each holding the largest
 // intermediate (a fused pass skips a step, so either buffer may receive any
 // intermediate); a launch always writes the buffer its input is not in.

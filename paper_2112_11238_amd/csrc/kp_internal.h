@@ -18,6 +18,11 @@ ModeArgs mode_args(const void* X, void* Y, const int64_t* dims, int d, int mu0,
                    const kp_matrix& L, int accumulate);
 size_t elem_size(int dtype);
 size_t align_up(size_t x);
+// Argument checks shared by the entry points (kp_api.hip): KP_OK or an error.
+int check_tensor(const kp_tensor* t, bool need_data);
+int check_matrix(const kp_matrix* L, int dtype);
+bool overlaps(const void* a, size_t abytes, const void* b, size_t bbytes);
+size_t matrix_span_bytes(const kp_matrix& L);
 
 // Factor-gradient contraction (gram_kernels.hip): dL(i,j) = sum_r Q(r,i) P(r,j)
 // over the fibers of the views Q (Il, n, Ir) and P (Il, m, Ir), written at

@@ -271,6 +271,88 @@ def expm(A, tau=1.0):
     return E if batched else E[0]
 
 
+def _f64_device(*ts):
+    _check_device(*ts)
+    for t in ts:
+        if t is not None and t.dtype != torch.float64:
+            raise TypeError("this operation runs in float64")
+
+
+def tridiag_inverse(lower, diag, upper, shift=0.0, scale=1.0):
+    """(shift I + scale T)^{-1} in FP64 on the device for the tridiagonal T
+    with T[i, i-1] = lower[i], T[i, i] = diag[i], T[i, i+1] = upper[i]
+    (vectors of length n, or (count, n) for a batch); elimination without
+    pivoting per identity column (kp_tridiag_inverse_f64). With shift=1,
+    scale=-tau this is an ADI factor (I - tau A)^{-1}."""
+    _f64_device(lower, diag, upper)
+    batched = diag.dim() == 2
+    lo, dg, up = [(x if batched else x.unsqueeze(0)).contiguous() for x in (lower, diag, upper)]
+    if not (lo.shape == dg.shape == up.shape) or dg.dim() != 2:
+        raise ValueError("diagonals must share the shape (n,) or (count, n)")
+    count, n = dg.shape
+    E = torch.empty((count, n, n), dtype=torch.float64, device=dg.device)
+    st = lib().kp_tridiag_inverse_f64(lo.data_ptr(), dg.data_ptr(), up.data_ptr(), n, count,
+                                      float(shift), float(scale), E.data_ptr(), _stream())
+    check(st, "kp_tridiag_inverse_f64")
+    E = E.transpose(1, 2)  # the library writes column-major matrices
+    return E if batched else E[0]
+
+
+def pcg_kronsum(B, Ms, Ps=None, x0=None, tol=1e-5, maxit=1000):
+    """Solve (M_d (+) ... (+) M_1) x = b (the Kronecker sum acting on B as
+    sum_mu B x_mu M_mu) by preconditioned conjugate gradients in FP64 with the
+    preconditioner action R x_1 Ps[0] ... x_d Ps[d-1] (Ps None: plain CG; a
+    None entry: identity), from x0 (zeros if None). Returns (X, iterations,
+    relative residual). Blocks until done (kp_pcg_kronsum)."""
+    _f64_device(B, x0, *Ms, *(Ps or []))
+    d = B.dim()
+    if len(Ms) != d or (Ps is not None and len(Ps) != d):
+        raise ValueError(f"need {d} matrices per list")
+    Bc = _canon(B)
+    X = torch.zeros_like(Bc) if x0 is None else _canon(x0).clone()
+    bd, xd = _tdesc(Bc, True), _tdesc(X, True)
+    marr = _mlist([_mdesc(M) for M in Ms][::-1])
+    parr = None if Ps is None else _mlist([None if Pm is None else _mdesc(Pm) for Pm in Ps][::-1])
+    lb = lib()
+    ws_bytes = lb.kp_pcg_workspace(ctypes.byref(xd), parr)
+    ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=B.device)
+    it, res = ctypes.c_int(0), ctypes.c_double(0.0)
+    st = lb.kp_pcg_kronsum(ctypes.byref(bd), marr, parr, ctypes.byref(xd), float(tol), int(maxit),
+                           ws.data_ptr(), ws_bytes, ctypes.byref(it), ctypes.byref(res), _stream())
+    check(st, "kp_pcg_kronsum")
+    return X, it.value, res.value
+
+
+def semilinear_imex(U, lower, diag, upper, h, tau, steps, t0=0.0, tol=1e-5, maxit=1000,
+                    precondition=True):
+    """Backward-forward Euler steps of the semilinear experiment on the
+    device, in place on U (axis mu-1 = x_mu, interior grid points
+    x = (i+1) h[mu]): lower/diag/upper[mu] are the diagonals of the second
+    difference of axis mu (device vectors). Returns the PCG iterations of
+    each step (kp_semilinear_imex_f64)."""
+    _f64_device(U, *lower, *diag, *upper)
+    d = U.dim()
+    if not (len(lower) == len(diag) == len(upper) == len(h) == d):
+        raise ValueError(f"need {d} diagonals and spacings")
+    if not U.is_contiguous():
+        raise ValueError("U must be contiguous (it is updated in place)")
+    ud = _tdesc(U, True)
+    vecs = [[v.contiguous() for v in arr][::-1] for arr in (lower, diag, upper)]
+    ptrs = [(ctypes.c_void_p * d)(*[v.data_ptr() for v in arr]) for arr in vecs]
+    hs = (ctypes.c_double * d)(*[float(x) for x in h][::-1])
+    dims = (ctypes.c_int64 * d)(*list(U.shape)[::-1])
+    lb = lib()
+    ws_bytes = lb.kp_semilinear_workspace(d, dims)
+    ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=U.device)
+    its = (ctypes.c_int * max(int(steps), 1))()
+    st = lb.kp_semilinear_imex_f64(ctypes.byref(ud), ptrs[0], ptrs[1], ptrs[2], hs, float(t0),
+                                   float(tau), int(steps), float(tol), int(maxit),
+                                   1 if precondition else 0, ws.data_ptr(), ws_bytes, its,
+                                   _stream())
+    check(st, "kp_semilinear_imex_f64")
+    return [its[k] for k in range(int(steps))]
+
+
 class BatchedTucker:
     """Many independent Tucker operators (and optionally their gradients):
     one persistent launch per dependency level and task type

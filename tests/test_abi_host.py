@@ -231,6 +231,73 @@ def test_expm_argument_errors(lib):
     assert lib.kp_expm_f64(FAKE, 0, 1, 1.0, FAKE * 2, None, 0, None) == 0
 
 
+@no_device
+def test_tridiag_inverse_argument_errors(lib):
+    f = lib.kp_tridiag_inverse_f64
+    lo, dg, up, E = FAKE, FAKE + 0x1000, FAKE + 0x2000, FAKE + 0x100000
+    assert f(lo, dg, up, 2049, 1, 1.0, -1.0, E, None) == -4
+    assert f(lo, dg, up, -1, 1, 1.0, -1.0, E, None) == -4
+    assert f(lo, dg, up, 4, 65536, 1.0, -1.0, E, None) == -4
+    assert f(None, dg, up, 4, 1, 1.0, -1.0, E, None) == -1
+    assert f(lo, dg, up, 4, 1, 1.0, -1.0, None, None) == -1
+    assert f(lo, dg, up, 4, 1, float("inf"), -1.0, E, None) == -9
+    assert f(lo, dg, up, 4, 1, 1.0, float("nan"), E, None) == -9
+    assert f(lo, dg, up, 4, 1, 1.0, -1.0, dg + 8, None) == -6
+    assert f(lo, dg, up, 0, 1, 1.0, -1.0, E, None) == 0
+
+
+@no_device
+def test_pcg_argument_errors(lib, L):
+    B = tensor(L, [4, 5, 6])
+    X = tensor(L, [4, 5, 6], data=FAKE + 0x200000)
+    Ms = [matrix(L, k, k, data=FAKE + 0x400000 + 0x1000 * j) for j, k in enumerate([4, 5, 6])]
+    Ps = [matrix(L, k, k, data=FAKE + 0x500000 + 0x1000 * j) for j, k in enumerate([4, 5, 6])]
+    wsb = lib.kp_pcg_workspace(ctypes.byref(X), mlist(L, Ps))
+    assert wsb >= 4 * 120 * 8 and lib.kp_pcg_workspace(ctypes.byref(X), None) < wsb
+    ws = FAKE + 0x800000
+
+    def call(b=B, m=Ms, p=Ps, x=X, tol=1e-5, maxit=10, w=ws, nb=wsb):
+        return lib.kp_pcg_kronsum(ctypes.byref(b), mlist(L, m), None if p is None else mlist(L, p),
+                                  None if x is None else ctypes.byref(x), tol, maxit, w, nb,
+                                  None, None, None)
+    assert call(x=None) == -1
+    assert call(m=[Ms[0], None, Ms[2]]) == -1
+    assert call(m=[Ms[0], matrix(L, 5, 4), Ms[2]]) == -4
+    assert call(p=[Ps[0], matrix(L, 4, 4), Ps[2]]) == -4
+    assert call(x=tensor(L, [4, 5, 7], data=FAKE + 0x200000)) == -4
+    assert call(b=tensor(L, [4, 5, 6], dtype=1), x=tensor(L, [4, 5, 6], dtype=1)) == -5
+    assert call(tol=-1.0) == -9 and call(tol=float("nan")) == -9 and call(maxit=-1) == -9
+    assert call(nb=wsb - 1) == -7 and call(w=None) == -7
+    assert call(x=tensor(L, [4, 5, 6], data=FAKE + 8)) == -6          # X overlaps B
+    assert call(x=tensor(L, [4, 5, 6], data=ws + 64)) == -6            # X overlaps ws
+
+
+@no_device
+def test_semilinear_argument_errors(lib, L):
+    dims = (ctypes.c_int64 * 3)(4, 5, 6)
+    wsb = lib.kp_semilinear_workspace(3, dims)
+    assert wsb > 0
+    assert lib.kp_semilinear_workspace(3, (ctypes.c_int64 * 3)(4, 0, 6)) == 0
+    assert lib.kp_semilinear_workspace(3, (ctypes.c_int64 * 3)(4, 3000, 6)) == 0
+    ptr = lambda base: (ctypes.c_void_p * 3)(*[base + 0x1000 * k for k in range(3)])
+    lo, dg, up = ptr(FAKE + 0x300000), ptr(FAKE + 0x310000), ptr(FAKE + 0x320000)
+    h = (ctypes.c_double * 3)(0.2, 1 / 6, 1 / 7)
+    ws = FAKE + 0x800000
+
+    def call(u=None, lo=lo, dg=dg, up=up, h=h, tau=0.01, steps=3, tol=1e-5, maxit=10, w=ws,
+             nb=wsb):
+        u = tensor(L, [4, 5, 6]) if u is None else u
+        return lib.kp_semilinear_imex_f64(ctypes.byref(u), lo, dg, up, h, 0.0, tau, steps, tol,
+                                          maxit, 1, w, nb, None, None)
+    assert call(u=tensor(L, [4, 5, 6], dtype=1)) == -5
+    assert call(u=tensor(L, [4, 5, 3000])) == -4
+    assert call(lo=(ctypes.c_void_p * 3)(FAKE, None, FAKE)) == -1
+    assert call(h=(ctypes.c_double * 3)(0.2, -1.0, 0.1)) == -9
+    assert call(tau=float("inf")) == -9 and call(steps=-1) == -9 and call(maxit=-1) == -9
+    assert call(nb=wsb - 1) == -7
+    assert call(u=tensor(L, [4, 5, 6], data=ws + 8)) == -6
+
+
 def test_force_tile_argument_errors(lib):
     assert lib.kp_force_tile(4, 0, 16, 0, 0, 0) == -9
     assert lib.kp_force_tile(4, 1, 16, 0, 3, 0) == -9

@@ -1,0 +1,123 @@
+"""The semilinear experiment on the device (Sec. 3.4 and 4.5): tridiagonal
+inverses, PCG on a Kronecker-sum system and the backward-forward Euler run,
+each against the oracle on the same inputs."""
+import numpy as np
+import pytest
+import torch
+
+import kp_workloads
+import oracle
+from gpu_util import say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def kp():
+    import paper_2112_11238_amd as kp
+    return kp
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+@pytest.mark.parametrize("n", [1, 2, 48, 257, 600])
+def test_tridiag_inverse_matches_oracle(kp, n):
+    rng = np.random.default_rng(n)
+    count = 3
+    lo, up = rng.standard_normal((count, n)), rng.standard_normal((count, n))
+    dg = 3.0 + rng.random((count, n))             # diagonally dominant
+    for shift, scale in [(0.0, 1.0), (1.0, -0.5)]:
+        say("tridiag_inverse", n, count, shift, scale)
+        E = kp.tridiag_inverse(to_dev(lo, torch.float64), to_dev(dg, torch.float64),
+                               to_dev(up, torch.float64), shift=shift, scale=scale)
+        torch.cuda.synchronize()
+        for k in range(count):
+            ref = oracle.tridiag_inverse(scale * lo[k], shift + scale * dg[k], scale * up[k])
+            assert _rel(E[k].cpu().numpy(), ref) <= 1e-13 * max(n, 4)
+
+
+def test_adi_factor_inverse(kp):
+    n, tau = 48, 0.01
+    lo, dg, up, h = kp_workloads.second_difference_diagonals(n)
+    E = kp.tridiag_inverse(*[to_dev(v, torch.float64) for v in (lo, dg, up)], shift=1.0,
+                           scale=-tau)
+    torch.cuda.synchronize()
+    ref = oracle.tridiag_inverse(-tau * lo, 1.0 - tau * dg, -tau * up)
+    assert _rel(E.cpu().numpy(), ref) <= 1e-13
+
+
+PCG_CASES = [(4, 5, 6), (7, 130, 9), (40, 44, 48)]
+
+
+@pytest.mark.parametrize("case", range(len(PCG_CASES)))
+@pytest.mark.parametrize("pre", [True, False])
+def test_pcg_matches_oracle(kp, case, pre):
+    ns = PCG_CASES[case]
+    Ms = kp_workloads.spd_matrices(100 + case, ns)
+    Ps = kp_workloads.spd_matrices(200 + case, ns, shift=0.5) if pre else None
+    B = np.random.default_rng(300 + case).standard_normal(ns)
+    tol = 1e-10
+    say("pcg", ns, pre)
+    X, it, res = kp.pcg_kronsum(to_dev(B, torch.float64), [to_dev(M, torch.float64) for M in Ms],
+                                None if Ps is None else [to_dev(P, torch.float64) for P in Ps],
+                                tol=tol, maxit=500)
+    torch.cuda.synchronize()
+    rx, rit, rres = oracle.pcg(lambda v: oracle.kronsumv(v, Ms), B, np.zeros(ns),
+                               None if Ps is None else (lambda r: oracle.tucker(r, Ps)), tol, 500)
+    assert res <= tol and abs(it - rit) <= 1, (it, rit)
+    assert _rel(X.cpu().numpy(), rx) <= 1e-8
+
+
+def test_pcg_degenerate_cases(kp):
+    ns = (5, 6, 7)
+    Ms = [to_dev(M, torch.float64) for M in kp_workloads.spd_matrices(7, ns)]
+    X, it, res = kp.pcg_kronsum(torch.zeros(ns, dtype=torch.float64, device="cuda"), Ms,
+                                x0=torch.ones(ns, dtype=torch.float64, device="cuda"))
+    torch.cuda.synchronize()
+    assert it == 0 and res == 0.0 and torch.count_nonzero(X).item() == 0
+    B = torch.randn(ns, dtype=torch.float64, device="cuda")
+    X1, it1, _ = kp.pcg_kronsum(B, Ms, tol=1e-13, maxit=500)
+    X2, it2, res2 = kp.pcg_kronsum(B, Ms, x0=X1, tol=1e-6)     # converged start
+    torch.cuda.synchronize()
+    assert it1 > 0 and it2 == 0 and res2 <= 1e-6 and torch.equal(X1, X2)
+    X3, it3, res3 = kp.pcg_kronsum(B, Ms, tol=1e-13, maxit=2)  # stops at maxit
+    assert it3 == 2 and res3 > 1e-13
+
+
+@pytest.mark.parametrize("pre", [True, False])
+def test_imex_short_run_matches_oracle(kp, pre):
+    ns, tau, steps, t0 = (5, 7, 9), 0.05, 3, 0.3
+    u0, diags, _, _ = kp_workloads.semilinear(ns)
+    U = to_dev(u0, torch.float64)
+    say("imex short", ns, pre)
+    its = kp.semilinear_imex(U, *[[to_dev(dd[j], torch.float64) for dd in diags] for j in range(3)],
+                             [dd[3] for dd in diags], tau, steps, t0=t0, tol=1e-10,
+                             precondition=pre)
+    torch.cuda.synchronize()
+    ref, rits = oracle.semilinear_imex(ns, tau=tau, steps=steps, tol=1e-10, precondition=pre,
+                                       u=u0, t0=t0)
+    assert all(abs(a - b) <= 1 for a, b in zip(its, rits)), (its, rits)
+    assert _rel(U.cpu().numpy(), ref) <= 1e-8
+
+
+def test_imex_experiment_reproduces_printed_results(kp):
+    """n = (40, 44, 48), tau = 0.01, t* = 1: relative max-norm error 9.7e-3,
+    two preconditioned iterations per step on average."""
+    u0, diags, tau, steps = kp_workloads.semilinear()
+    ns = u0.shape
+    U = to_dev(u0, torch.float64)
+    say("imex experiment", ns)
+    its = kp.semilinear_imex(U, *[[to_dev(dd[j], torch.float64) for dd in diags] for j in range(3)],
+                             [dd[3] for dd in diags], tau, steps)
+    torch.cuda.synchronize()
+    u = U.cpu().numpy()
+    ref, rits = oracle.semilinear_imex(ns, tau=tau, steps=steps)
+    xs = [oracle.semilinear_grid(n)[0] for n in ns]
+    exact = np.exp(1.0) * oracle.semilinear_u0(xs)
+    err = np.max(np.abs(u - exact)) / np.max(np.abs(exact))
+    assert 9.65e-3 <= err <= 9.8e-3, err
+    assert round(np.mean(its)) == 2, np.mean(its)
+    assert sum(a != b for a, b in zip(its, rits)) <= 2, (its, rits)
+    assert _rel(u, ref) <= 1e-7
