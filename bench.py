@@ -57,7 +57,7 @@ def parse():
     ap.add_argument("--forms", default="all", help="comma list of f64,f32,bf16x3,bf16x6")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--workload", default="cube200",
-                    choices=["cube200", "small2d", "heat128", "interp6d", "batch64"],
+                    choices=["cube200", "small2d", "heat128", "interp6d", "batch64", "semilinear"],
                     help="cube200 is the headline line; the others time the remaining "
                          "configurations (one JSON line each)")
     ap.add_argument("--autotune", action="store_true",
@@ -567,8 +567,88 @@ def bench_batch64(args):
                  {"forms": forms})
 
 
+def bench_semilinear(args):
+    """The semilinear experiment (n = (40, 44, 48), tau = 0.01, 100 steps to
+    t = 1): ADI factor inverses built on the device, one PCG solve per step
+    on the Kronecker-sum matrix; also plain CG. Each timed run starts from u0."""
+    import torch
+
+    import oracle
+    import paper_2112_11238_amd as kp
+    u0, diags, tau, nsteps = kp_workloads.semilinear()
+    ns = u0.shape
+    N = int(np.prod(ns))
+    dev = [[torch.tensor(dd[j], dtype=torch.float64, device="cuda") for dd in diags]
+           for j in range(3)]
+    hs = [dd[3] for dd in diags]
+    xs = [oracle.semilinear_grid(n)[0] for n in ns]
+    exact = np.exp(1.0) * oracle.semilinear_u0(xs)
+    runs = max(1, min(args.steps, 5))
+    tuned = None
+    if args.autotune:
+        # the preconditioner and Kronecker-sum products share their views
+        Ud = torch.tensor(u0, dtype=torch.float64, device="cuda")
+        sq = [torch.randn((n, n), dtype=torch.float64, device="cuda") for n in ns]
+        tuned = kp.tune.autotune(Ud, sq, reps=20)
+    out = {}
+    finals = {}
+    for pre in (True, False):
+        U = torch.tensor(u0, dtype=torch.float64, device="cuda")
+        kp.semilinear_imex(U, *dev, hs, tau, nsteps, precondition=pre)   # warm-up
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(runs):
+            U.copy_(torch.tensor(u0, dtype=torch.float64, device="cuda"))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            its = kp.semilinear_imex(U, *dev, hs, tau, nsteps, precondition=pre)
+            torch.cuda.synchronize()
+            times.append((time.perf_counter() - t0) * 1e3)
+        ms = statistics.median(times)
+        u = U.cpu().numpy()
+        finals[pre] = u
+        total_its = int(sum(its))
+        out["pcg" if pre else "cg"] = {
+            "ms_per_run": round(ms, 3), "avg_iterations": round(total_its / nsteps, 3),
+            "us_per_iteration": round(ms * 1e3 / max(total_its + nsteps, 1), 2),
+            "rel_err_vs_exact_maxnorm": float(np.abs(u - exact).max() / np.abs(exact).max())}
+    cpu = None
+    if not args.no_cpu_baseline:
+        t0 = time.perf_counter()
+        ref, rits = oracle.semilinear_imex(ns, tau=tau, steps=nsteps)
+        cpu_ms = (time.perf_counter() - t0) * 1e3
+        out["pcg"]["rel_diff_vs_oracle"] = _rel(finals[True], ref)
+        cpu = {"value": round(cpu_ms, 1), "unit": "ms", "cores": _threads(), "kind": "oracle",
+               "sample": "one whole oracle run (100 PCG steps)"}
+    head = out["pcg"]
+    # per PCG iteration the vectors of length N cross memory about 30 times
+    # (3 preconditioner products and 3 Kronecker-sum products, each reading
+    # and writing N; the accumulating products read N more; dot products and
+    # updates): 30 N doubles; the run is launch- and sync-latency bound
+    it_bytes = 30 * N * 8
+    achieved = it_bytes / (head["us_per_iteration"] * 1e-6) / 1e9
+    extra = {"solvers": out, "paper_context": {"pcg_tensor_s": 0.5, "cg_tensor_s": 2.2,
+                                               "avg_iterations_pcg": 2, "avg_iterations_cg": 30,
+                                               "rel_err": 9.7e-3, "hardware": "the paper's CPU"},
+             "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                          "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
+                          "traffic": None}}
+    if cpu:
+        extra["cpu_baseline"] = cpu
+    if tuned is not None:
+        extra["tuned_tiles"] = tuned
+    return _line(args, "semilinear experiment wall time (n=(40,44,48), tau=0.01, 100 "
+                       "backward-forward Euler steps, ADI-preconditioned CG)",
+                 head["ms_per_run"], "ms", head["ms_per_run"], "f64",
+                 {"workload": "semilinear: u_t = Laplacian u + 1/(1+u^2) + Phi on [0,1]^3, "
+                              "Dirichlet, n = (40, 44, 48) interior points, tau = 0.01, t* = 1, "
+                              "u0 = prod x(1-x), PCG tol 1e-5; value is ms per whole run",
+                  "elements": N}, extra, higher=False)
+
+
 WORKLOAD_BENCHES = {"small2d": bench_small2d, "heat128": bench_heat128,
-                    "interp6d": bench_interp6d, "batch64": bench_batch64}
+                    "interp6d": bench_interp6d, "batch64": bench_batch64,
+                    "semilinear": bench_semilinear}
 
 
 if __name__ == "__main__":
