@@ -57,7 +57,8 @@ def parse():
     ap.add_argument("--forms", default="all", help="comma list of f64,f32,bf16x3,bf16x6")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--workload", default="cube200",
-                    choices=["cube200", "small2d", "heat128", "interp6d", "batch64", "semilinear"],
+                    choices=["cube200", "small2d", "heat128", "interp6d", "batch64", "semilinear",
+                             "runge5d", "codeval"],
                     help="cube200 is the headline line; the others time the remaining "
                          "configurations (one JSON line each)")
     ap.add_argument("--autotune", action="store_true",
@@ -567,6 +568,113 @@ def bench_batch64(args):
                  {"forms": forms})
 
 
+def bench_runge5d(args):
+    """The 5-D Runge interpolation at the paper's largest size: F on 45^5
+    Chebyshev nodes (1.48 GB in FP64) to 35^5 equispaced points, in FP64 and
+    the FP32 forms; error against the exact function values."""
+    import torch
+
+    import oracle
+    import paper_2112_11238_amd as kp
+    m, n, d = 45, 35, 5
+    F, Ls, x = kp_workloads.runge5d(m, n, d)
+    flops = kp_workloads.tucker_flops([m] * d, [n] * d)
+    f = oracle.runge(*([x] * d))
+    fmax = float(np.abs(f).max())
+    forms = {}
+    roof = None
+    for dt, prec in _form_list(args, FORMS):
+        tdt = torch.float64 if dt == "f64" else torch.float32
+        Fd = torch.tensor(F, dtype=tdt, device="cuda")
+        Ld = [torch.tensor(L, dtype=tdt, device="cuda") for L in Ls]
+        S = kp.tucker(Fd, Ld, prec=prec)
+        torch.cuda.synchronize()
+        err = float(np.abs(S.double().cpu().numpy() - f).max() / fmax)
+        del S
+        ms = _events_ms(lambda: kp.tucker(Fd, Ld, prec=prec), args.steps, args.warmup)
+        views = _views(kp, Fd, Ld, prec)
+        es = 8 if dt == "f64" else 4
+        modes = []
+        for Il, mm, nn, Ir in views:
+            lms = _launch_ms(kp, tdt, prec, (Il, mm, nn, Ir), args.steps)
+            byts = (Il * mm * Ir + Il * nn * Ir) * es
+            modes.append({"view": [Il, mm, nn, Ir], "ms": round(lms, 5),
+                          "gbs": round(byts / (lms * 1e-3) / 1e9, 1)})
+        forms[form_name(dt, prec)] = {
+            "ms_per_step": round(ms, 5), "tflops": round(flops / (ms * 1e-3) / 1e12, 3),
+            "rel_err_vs_runge_maxnorm": err, "modes": modes}
+        if dt == "f64" and prec == "native":
+            # the first (largest) product: 1.48 GB in, 1.15 GB out, 4.9 flop/B
+            g = modes[0]["gbs"]
+            roof = {"bound": "hbm", "achieved": g, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(g / HBM_PEAK_GBS, 4), "traffic": None}
+        del Fd
+        torch.cuda.empty_cache()
+    head = forms.get("f64") or next(iter(forms.values()))
+    extra = {"forms": forms, "paper_printed_rel_err_m45": 1.39e-5}
+    if roof:
+        extra["roofline"] = roof
+    if not args.no_cpu_baseline:
+        Fs, Lss, _ = kp_workloads.runge5d(35, n, d)
+        t0 = time.perf_counter()
+        oracle.tucker(Fs, Lss)
+        sec = time.perf_counter() - t0
+        sflops = kp_workloads.tucker_flops([35] * d, [n] * d)
+        extra["cpu_baseline"] = {"value": round(sflops / sec / 1e12, 6), "unit": "TFLOP/s",
+                                 "cores": _threads(), "kind": "oracle",
+                                 "sample": f"one oracle Tucker call at m=35 ({sec:.1f} s)"}
+    return _line(args, "Tucker-op TFLOP/s runge5d (d=5, 45^5 Chebyshev -> 35^5 uniform, FP64)",
+                 head["tflops"], "TFLOP/s", head["ms_per_step"], "f64",
+                 {"workload": "runge5d: Runge function 1/(1+16|x|^2) on 45^5 Chebyshev nodes, "
+                              "barycentric Lagrange factors to 35 equispaced points of [-1,1] "
+                              "per direction; value is the FP64 form", "flops_per_step": flops},
+                 extra)
+
+
+def bench_codeval(args):
+    """The paper's Tucker timing sweep shapes: d = 3 with n in {144, 196,
+    256, 324} and d = 6 with n in {12, 14, 16, 18}, square standard-normal
+    factors, in every form."""
+    import torch
+
+    import oracle
+    import paper_2112_11238_amd as kp
+    shapes = {}
+    for d, n in kp_workloads.codeval_shapes():
+        T, Ls = kp_workloads.cube(seed=n, n=n, d=d)
+        flops = kp_workloads.tucker_flops([n] * d, [n] * d)
+        rec = {}
+        for dt, prec in _form_list(args, FORMS):
+            tdt = torch.float64 if dt == "f64" else torch.float32
+            Td = torch.tensor(T, dtype=tdt, device="cuda")
+            Ld = [torch.tensor(L, dtype=tdt, device="cuda") for L in Ls]
+            ms = _events_ms(lambda: kp.tucker(Td, Ld, prec=prec), args.steps, args.warmup)
+            tf = flops / (ms * 1e-3) / 1e12
+            peak = PEAK["f64"] if dt == "f64" else (PEAK["f32"] if prec == "native"
+                                                    else PEAK["bf16"])
+            rec[form_name(dt, prec)] = {"ms": round(ms, 5), "tflops": round(tf, 3),
+                                        "frac_of_form_peak": round(tf / peak, 4)}
+        shapes[f"d{d}_n{n}"] = {"flops": flops, "forms": rec}
+    head = shapes["d3_n324"]["forms"].get("f64") or next(iter(shapes["d3_n324"]["forms"].values()))
+    extra = {"shapes": shapes, "paper_context": {"d3_gflops_cpu": [106, 127],
+                                                 "d6_gflops_cpu": [11, 14],
+                                                 "hardware": "the paper's CPU"}}
+    if not args.no_cpu_baseline:
+        T, Ls = kp_workloads.cube(seed=196, n=196, d=3)
+        t0 = time.perf_counter()
+        oracle.tucker(T, Ls)
+        sec = time.perf_counter() - t0
+        extra["cpu_baseline"] = {"value": round(kp_workloads.tucker_flops([196] * 3, [196] * 3)
+                                                / sec / 1e12, 6), "unit": "TFLOP/s",
+                                 "cores": _threads(), "kind": "oracle",
+                                 "sample": f"one oracle Tucker call at d=3 n=196 ({sec:.2f} s)"}
+    return _line(args, "Tucker-op TFLOP/s codeval sweep (d=3 n=144..324, d=6 n=12..18), "
+                       "value at d=3 n=324 FP64",
+                 head["tflops"], "TFLOP/s", head["ms"], "f64",
+                 {"workload": "codeval: standard-normal cubes and square factors, seed = n, "
+                              "d=3 n in {144,196,256,324}, d=6 n in {12,14,16,18}"}, extra)
+
+
 def bench_semilinear(args):
     """The semilinear experiment (n = (40, 44, 48), tau = 0.01, 100 steps to
     t = 1): ADI factor inverses built on the device, one PCG solve per step
@@ -648,7 +756,8 @@ def bench_semilinear(args):
 
 WORKLOAD_BENCHES = {"small2d": bench_small2d, "heat128": bench_heat128,
                     "interp6d": bench_interp6d, "batch64": bench_batch64,
-                    "semilinear": bench_semilinear}
+                    "semilinear": bench_semilinear, "runge5d": bench_runge5d,
+                    "codeval": bench_codeval}
 
 
 if __name__ == "__main__":

@@ -24,6 +24,10 @@ Table 1 and Sec. 4.1; its applications supply structured factors):
                 points of [-1, 1] (Sec. 4.3 shape, with d=6).
 * ``batch64``   64 tensors of order 4, each mode size uniform in [16, 64],
                 square factors with entries N(0,1)/sqrt(n_mu).
+* ``runge5d``   d=5 Runge function on m^5 Chebyshev nodes, Lagrange matrices
+                to 35 equispaced points (Sec. 4.3, m = 5..45).
+* ``codeval``   standard-normal cubes of the paper's timing sweep, d=3
+                n = 144..324 and d=6 n = 12..18 (use ``cube(seed, n, d)``).
 * ``semilinear`` the semilinear diffusion-reaction experiment (Sec. 4.5):
                 grids of n = (40, 44, 48) interior points, the diagonals of
                 each second difference, the initial value
@@ -140,6 +144,30 @@ def lagrange_chebyshev_to_uniform(m=16, n=24):
             r = w / diff
             L[l] = r / r.sum()
     return L
+
+
+def runge5d(m, n=35, d=5):
+    """(F, [L] * d, x): the d-variate Runge function 1/(1 + 16 sum_mu x_mu^2)
+    sampled on the m^d grid of Chebyshev nodes (axis mu-1 = x_mu), the n x m
+    Lagrange matrix from those nodes to the n equispaced points x of [-1, 1],
+    and x (Sec. 4.3, the 5-D interpolation example)."""
+    i = np.arange(1, m + 1)
+    xi = np.cos((2 * i - 1) * np.pi / (2.0 * m))
+    acc = xi ** 2
+    for _ in range(d - 1):
+        acc = np.add.outer(acc, xi ** 2)
+    acc *= 16.0
+    acc += 1.0
+    F = np.reciprocal(acc, out=acc)
+    L = lagrange_chebyshev_to_uniform(m, n)
+    return F, [L.copy() for _ in range(d)], np.linspace(-1.0, 1.0, n)
+
+
+def codeval_shapes():
+    """The shapes of the paper's timing sweep of the Tucker operator: d = 3
+    with n in {144, 196, 256, 324} and d = 6 with n in {12, 14, 16, 18}
+    (square factors)."""
+    return [(3, n) for n in (144, 196, 256, 324)] + [(6, n) for n in (12, 14, 16, 18)]
 
 
 def interp6d(seed=SEED, m=16, n=24, d=6):
