@@ -212,10 +212,9 @@ hipError_t launch_mode(int form, const ModeArgs& a, const ModeTile* force,
   const int64_t bf = 64 * t.fb;
   const int64_t bn = 16 * t.nb;
   // 16-byte group loads: L k-contiguous with 16-byte aligned rows, m a
-  // multiple of the group (so the k tail is whole groups), and for the lead
-  // layout X rows (m elements) 16-byte aligned too
-  const int64_t kv = form == FORM_F64 ? 2 : (form == FORM_F32 ? 4 : 8);
-  const bool vec_l = a.cs == 1 && (a.rs * es) % 16 == 0 && a.m % kv == 0 &&
+  // multiple of 16 bytes' worth of elements (so the k tail is whole 16-byte
+  // pieces), and for the lead layout X rows (m elements) 16-byte aligned too
+  const bool vec_l = a.cs == 1 && (a.rs * es) % 16 == 0 && (a.m * es) % 16 == 0 &&
                      reinterpret_cast<uintptr_t>(a.L) % 16 == 0;
   const bool xrow16 = (a.m * es) % 16 == 0;
   for (int64_t b0 = 0; b0 < a.Ir; b0 += per) {

@@ -163,8 +163,9 @@ constexpr size_t mode_lds_bytes() {
 // alternate so the global loads of chunk c+2 are in flight while chunk c
 // computes (LDS stays double buffered).
 // VEC: L is k-contiguous (cs = 1) and, in the lead layout, so is X; every
-// KV-element group then starts 16-byte aligned and m is a multiple of KV, so
-// each group is loaded with 16-byte loads (the host checks these conditions).
+// KV-element group then starts 16-byte aligned and m is a multiple of 16
+// bytes' worth of elements, so each group is loaded with 16-byte loads (the
+// host checks these conditions).
 template <int FORM, int NB, int FB, int BK, bool INNER, int PF = 1, bool VEC = false>
 __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t bx, int64_t by,
                                           char* __restrict__ lds) {
@@ -271,15 +272,18 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t bx, int64_t
         const_cast<char*>(reinterpret_cast<const char*>(X)) + xk, 0, x_bytes - xk, kBufferFlags);
     const auto lrs = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<char*>(reinterpret_cast<const char*>(L)) + lk, 0, l_bytes - lk, kBufferFlags);
-    // a group of KV k values as 16-byte loads (a whole group is valid or not:
-    // m is a multiple of KV)
-    auto load_group = [&](__amdgpu_buffer_rsrc_t rs, uint32_t off, G (&dst)[KV]) {
+    // a group of KV k values (first k = kb) as 16-byte loads; m is a multiple
+    // of 16 bytes' worth of elements, so each 16-byte piece is wholly inside
+    // or wholly past k = m (checked on the tail chunk only)
+    auto load_group = [&](__amdgpu_buffer_rsrc_t rs, uint32_t off, int64_t kb, G (&dst)[KV]) {
       typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
       constexpr int NQ = KV * sizeof(G) / 16;
+      constexpr int PER = 16 / sizeof(G);
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
-        const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(
-            rs, static_cast<int>(off == kOut ? kOut : off + 16 * q), 0, 0);
+        uint32_t o = off + 16 * q;
+        if constexpr (CHECK) o = kb + q * PER < m ? o : kOut;
+        const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, static_cast<int>(o), 0, 0);
         typedef G g16 __attribute__((ext_vector_type(16 / sizeof(G))));
         const g16 gv = __builtin_bit_cast(g16, v);
 #pragma unroll
@@ -290,9 +294,7 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t bx, int64_t
 #pragma unroll
     for (int s = 0; s < XT; ++s) {
       if constexpr (VEC && !INNER) {
-        uint32_t off = xo[s][0];
-        if constexpr (CHECK) off = k0 + xkg[s] * KV < m ? off : kOut;
-        load_group(xrs, off, xr[SET][s]);
+        load_group(xrs, xo[s][0], k0 + xkg[s] * KV, xr[SET][s]);
       } else {
 #pragma unroll
         for (int e = 0; e < KV; ++e) {
@@ -305,9 +307,7 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t bx, int64_t
 #pragma unroll
     for (int s = 0; s < LT; ++s) {
       if constexpr (VEC) {
-        uint32_t off = lo_[s][0];
-        if constexpr (CHECK) off = k0 + lkg[s] * KV < m ? off : kOut;
-        load_group(lrs, off, lr[SET][s]);
+        load_group(lrs, lo_[s][0], k0 + lkg[s] * KV, lr[SET][s]);
       } else {
 #pragma unroll
         for (int e = 0; e < KV; ++e) {

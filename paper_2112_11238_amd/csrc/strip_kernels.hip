@@ -126,9 +126,8 @@ hipError_t launch_strip(int form, const ModeArgs& a, const ModeTile& t, hipStrea
   const int64_t F = inner ? a.Il * a.Ir : a.Ir;
   if (F == 0 || a.n == 0) return hipSuccess;
   const int64_t es = form == FORM_F64 ? 8 : 4;
-  const int kv = form == FORM_F64 ? 2 : (form == FORM_F32 ? 4 : 8);
   // lead layout: 16-byte loads when every fiber row starts 16-byte aligned
-  const bool vec = !inner && (a.m % kv) == 0 && ((a.m * es) % 16) == 0 &&
+  const bool vec = !inner && ((a.m * es) % 16) == 0 &&
                    (reinterpret_cast<uintptr_t>(a.X) % 16) == 0;
   const StripFn fn = inner ? v->inner : (vec ? v->lead_vec : v->lead);
   const int64_t bf = 64 * v->fb, bn = 16 * v->nb;

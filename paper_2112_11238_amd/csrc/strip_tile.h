@@ -22,8 +22,9 @@ constexpr size_t strip_lds_bytes() {
 }
 
 // Fiber tiles bx = t0, t0 + tstep, ... < ntiles of n block `by`.
-// VEC (lead layout only): every fiber row starts 16-byte aligned and m is a
-// multiple of KV, so each staging task is one 16-byte load.
+// VEC (lead layout only): every fiber row starts 16-byte aligned (m is a
+// multiple of 16 bytes' worth of elements), so each staging task is a few
+// 16-byte loads.
 template <int FORM, int NB, int FB, int KP, bool INNER, bool VEC>
 __device__ __forceinline__ void strip_run(const ModeArgs& a, int64_t by, int64_t t0,
                                           int64_t tstep, int64_t ntiles,
@@ -142,11 +143,11 @@ __device__ __forceinline__ void strip_run(const ModeArgs& a, int64_t by, int64_t
         typedef G g16 __attribute__((ext_vector_type(16 / sizeof(G))));
         constexpr int NQ = KV * sizeof(G) / 16;
         constexpr int PER = 16 / sizeof(G);
-        const uint32_t off = kb < m ? (base + kb) * sizeof(G) : kOut;
+        // each 16-byte piece lies wholly inside or wholly past k = m
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
-          const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(
-              xrs, static_cast<int>(off == kOut ? kOut : off + 16 * q), 0, 0);
+          const uint32_t off = kb + q * PER < m ? (base + kb) * sizeof(G) + 16 * q : kOut;
+          const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(xrs, static_cast<int>(off), 0, 0);
           const g16 gv = __builtin_bit_cast(g16, v);
 #pragma unroll
           for (int e = 0; e < PER; ++e) xr[s][q * PER + e] = gv[e];

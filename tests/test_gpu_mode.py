@@ -120,13 +120,16 @@ TILES = {
 
 
 @pytest.mark.parametrize("dt,prec", FORMS)
-@pytest.mark.parametrize("shape", ["ragged", "aligned"])
+@pytest.mark.parametrize("shape", ["ragged", "aligned", "quad"])
 def test_every_tile_variant(kp, dt, prec, shape):
     # ragged: m not a multiple of the load group (element-wise loads);
     # aligned: contiguous factors with m a multiple of 8 and 16-byte rows, so
-    # the 16-byte group loads run (with a k tail of whole groups)
+    # the 16-byte group loads run (with a k tail of whole groups);
+    # quad: m a multiple of 4 but not of 8, so the BF16 forms' 8-element
+    # groups straddle k = m and their second 16-byte piece reads as zero
     key = prec if prec != "native" else ("native64" if dt == "f64" else "native32")
-    m, n = ((19, 45, 13), (7, 70, 29)) if shape == "ragged" else ((24, 40, 16), (7, 70, 29))
+    m = {"ragged": (19, 45, 13), "aligned": (24, 40, 16), "quad": (20, 44, 12)}[shape]
+    n = (7, 70, 29)
     T, Ls = kp_workloads.random_problem(11, m, n)
     T64 = cast64(T, DT[dt])
     try:
@@ -148,11 +151,13 @@ def test_every_tile_variant(kp, dt, prec, shape):
 
 def strip_cases(kp_len):
     """(torch shape, mode, layout) cases for a strip of padded length kp_len:
-    the lead layout with m = kp_len (16-byte loads) and with a k tail, the
+    the lead layout with m = kp_len (16-byte loads), with a k tail and with a
+    tail of whole 16-byte pieces (m = kp_len - 4), the
     innermost-strided layout and a middle mode; enough fibers that every
     workgroup streams several tiles."""
     m = kp_len
     return [((150001, m), 2, "lead"), ((150001, m - 3), 2, "lead tail"),
+            ((150001, m - 4), 2, "lead 16-byte tail"),
             ((m - 1, 300, 500), 1, "inner"), ((40, m, 3750), 2, "middle")]
 
 
