@@ -110,8 +110,9 @@ const Variant* find_variant(int form, const ModeTile& t) {
 }
 
 // Default tiles, chosen from tile sweeps on cube200 (m = n = 200), heat128
-// (n = 128) and small modes: FP64 favours 7 (or, at n = 128, 4) blocks along
-// n with 8-wide k chunks (small LDS and register footprint: 4 waves/SIMD);
+// (n = 128), the d = 3 n = 324 cube and small modes: FP64 favours 7 (or, at
+// n = 128, 4) blocks along n with 8-wide k chunks (small LDS and register
+// footprint: 4 waves/SIMD), with two chunks of loads in flight once m >= 256;
 // FP32 7 blocks (8 at n <= 128) with two chunks of loads in flight; the
 // BF16 split forms 4 blocks (BF16x6 with two chunks in flight). Short
 // contractions (m <= 64) take strip tiles.
@@ -129,6 +130,11 @@ ModeTile pick_tile(int form, int64_t m, int64_t n) {
       t.occ = 3;
       t.fb = 1;
       t.nb = (n <= 64 || (n > 112 && n <= 128)) ? 4 : 7;
+      // long contractions keep two chunks of loads in flight
+      if (t.nb == 7 && m >= 256) {
+        t.occ = 2;
+        t.pf = 2;
+      }
     }
   } else if (form == FORM_F32) {
     t.bk = 16;

@@ -432,7 +432,23 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t bx, int64_t
       store_chunk(0, Set0{});
     }
     __syncthreads();
-    for (int64_t ch = 0; ch < nchunks; ch += 2) {
+    int64_t ch = 0;
+    // Steady state: the two chunks loaded per pass (ch + 2, ch + 3) are full,
+    // so their loads carry no k check and sit in no branch; each LDS store
+    // then waits only for its own register set while the other set's loads
+    // stay in flight. Entry and exit state: LDS buffer 0 holds chunk ch and
+    // set 1 holds chunk ch + 1.
+    for (; ch + 3 < nfull; ch += 2) {
+      load_chunk((ch + 2) * BK, Unchecked{}, Set0{});
+      compute(0);
+      store_chunk(1, Set1{});
+      __syncthreads();
+      load_chunk((ch + 3) * BK, Unchecked{}, Set1{});
+      compute(1);
+      store_chunk(0, Set0{});
+      __syncthreads();
+    }
+    for (; ch < nchunks; ch += 2) {
       if (ch + 2 < nchunks) load(ch + 2, Set0{});
       compute(0);
       if (ch + 1 < nchunks) store_chunk(1, Set1{});

@@ -80,6 +80,8 @@ def test_set_lookup_list_clear(lib, L, tune):
     # default first
     tuned, tile = tune.lookup("f64", 40, 200, 200, 200)
     assert not tuned and tile[:3] == (7, 1, 8)
+    # long FP64 contractions keep two chunks of loads in flight
+    assert tune.lookup("f64", 1, 324, 324, 324 * 324) == (False, (7, 1, 8, 2, 2, 0))
     tune.set_tile("f64", 40, 200, 200, 200, (4, 1, 16))
     tuned, tile = tune.lookup("f64", 40, 200, 200, 200)
     assert tuned and tile[:3] == (4, 1, 16) and tile[3] > 0 and tile[4:] == (1, 0)  # resolved
