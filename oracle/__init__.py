@@ -19,6 +19,8 @@ approach for multidimensional tensor-structured problems"):
 * ``semilinear`` -- the semilinear diffusion-reaction experiment: tridiagonal
                   inverses (ADI factors), preconditioned conjugate gradients on
                   the Kronecker-sum matrix, backward-forward Euler steps.
+* ``complex_tucker`` -- the Tucker operator over C and its conjugate-transpose
+                  form (spectral transforms).
 * ``grad``     -- the gradient of a scalar loss through the Tucker operator
                   and a central finite-difference checker.
 
@@ -32,6 +34,7 @@ from .factors import (fd_laplacian_dirichlet, expm_fd_laplacian_dirichlet,
                       dst1_eigenpairs, chebyshev_nodes, chebyshev_weights,
                       lagrange_matrix, runge)
 from .grad import tucker_vjp, central_fd_directional
+from .complex_tucker import zmump, ztucker, cttucker, dft_matrix
 from .semilinear import (tridiag, tridiag_inverse, pcg, semilinear_grid, semilinear_u0,
                          semilinear_laplacian_u0, semilinear_phi, semilinear_rhs,
                          semilinear_factors, semilinear_imex)
@@ -42,6 +45,7 @@ __all__ = [
     "fd_laplacian_dirichlet", "expm_fd_laplacian_dirichlet", "dst1_eigenpairs",
     "chebyshev_nodes", "chebyshev_weights", "lagrange_matrix", "runge",
     "tucker_vjp", "central_fd_directional",
+    "zmump", "ztucker", "cttucker", "dft_matrix",
     "tridiag", "tridiag_inverse", "pcg", "semilinear_grid", "semilinear_u0",
     "semilinear_laplacian_u0", "semilinear_phi", "semilinear_rhs", "semilinear_factors",
     "semilinear_imex",
