@@ -145,6 +145,30 @@ int kp_tucker(const kp_tensor* T, const kp_matrix* const* L, kp_tensor* S,
               int prec, void* ws, size_t ws_bytes,
               void* cache, size_t cache_bytes, hipStream_t stream);
 
+/* ---- complex Tucker operator (Sec. 2 over C; Sec. 3 conjugate-transpose form) -
+ * A complex tensor is stored as interleaved (real, imaginary) pairs: T is a
+ * real kp_tensor (F64 or F32) of order d + 1 whose first mode has size 2;
+ * its modes 2..d+1 are the complex tensor's modes 1..d (d <= 7). Factor mu is
+ * L_mu = Lre[mu-1] + i Lim[mu-1], given as two real matrices of the same
+ * size (any strides, so an interleaved complex matrix is two views, element
+ * strides (2*cols, 2) offset by one element). Lre[k] == NULL together with
+ * Lim[k] == NULL is the identity; Lim[k] == NULL alone is a real factor.
+ *   conj == 0: S = T x_1 L_1 ... x_d L_d, L_mu is n_mu x m_mu;
+ *   conj != 0: S = T x_1 L_1^* ... x_d L_d^*, ^* the conjugate transpose,
+ *              L_mu is m_mu x n_mu.
+ * S is (2, n_1, ..., n_d) in the same layout. Modes are applied in order
+ * 1..d; each is two real mu-mode products on the real kernels (real and
+ * imaginary part of the factor) and one element-wise pass adding i times the
+ * second. prec as for kp_mump (the split forms need F32).
+ * ws_bytes >= kp_tucker_complex_workspace(...). Errors: as kp_tucker, and
+ * KP_ERR_ORDER for order < 2, KP_ERR_SHAPE if T's first mode is not 2 or the
+ * parts of a factor differ in size, KP_ERR_NULL for Lim[k] without Lre[k]. */
+size_t kp_tucker_complex_workspace(const kp_tensor* T, const kp_matrix* const* Lre,
+                                   const kp_matrix* const* Lim, int conj, int prec);
+int kp_tucker_complex(const kp_tensor* T, const kp_matrix* const* Lre,
+                      const kp_matrix* const* Lim, kp_tensor* S, int conj, int prec, void* ws,
+                      size_t ws_bytes, hipStream_t stream);
+
 /* ---- gradient of the Tucker operator ------------------------------------------
  * Given the cotangent G = dloss/dS (dims n_1..n_d):
  *   dT    = G x_1 L_1^T ... x_d L_d^T         (dims m_1..m_d)

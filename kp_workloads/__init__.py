@@ -163,6 +163,25 @@ def runge5d(m, n=35, d=5):
     return F, [L.copy() for _ in range(d)], np.linspace(-1.0, 1.0, n)
 
 
+def fourier_matrix(n):
+    """The n x n Fourier matrix exp(-2 pi i j k / n) (complex128), the basis
+    matrix of a discrete Fourier transform along one direction."""
+    j = np.arange(n)
+    return np.exp(-2j * np.pi * np.outer(j, j) / n)
+
+
+def complex_problem(seed, m_dims, n_dims, conj=False):
+    """Complex standard-normal T (real and imaginary parts N(0,1)) and
+    factors, n_mu x m_mu (m_mu x n_mu if conj); drawn T first."""
+    rng = np.random.default_rng(seed)
+    T = _normal(rng, tuple(m_dims)) + 1j * _normal(rng, tuple(m_dims))
+    Ls = []
+    for n, m in zip(n_dims, m_dims):
+        shape = (m, n) if conj else (n, m)
+        Ls.append(_normal(rng, shape) + 1j * _normal(rng, shape))
+    return T, Ls
+
+
 def codeval_shapes():
     """The shapes of the paper's timing sweep of the Tucker operator: d = 3
     with n in {144, 196, 256, 324} and d = 6 with n in {12, 14, 16, 18}

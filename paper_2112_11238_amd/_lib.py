@@ -74,6 +74,9 @@ SIGNATURES = {
     "kp_tucker_cache_size": (_S, [_T, _MA]),
     "kp_tucker_order": (ctypes.c_int, [_T, _MA, P(ctypes.c_int), P(ctypes.c_int)]),
     "kp_tucker": (ctypes.c_int, [_T, _MA, _T, ctypes.c_int, _V, _S, _V, _S, _V]),
+    "kp_tucker_complex_workspace": (_S, [_T, _MA, _MA, ctypes.c_int, ctypes.c_int]),
+    "kp_tucker_complex": (ctypes.c_int, [_T, _MA, _MA, _T, ctypes.c_int, ctypes.c_int, _V, _S,
+                                         _V]),
     "kp_tucker_backward_workspace": (_S, [_T, _MA, ctypes.c_int]),
     "kp_tucker_backward": (ctypes.c_int, [_T, _T, _MA, _V, _S, _T, _MA, ctypes.c_int,
                                           _V, _S, _V]),

@@ -1,0 +1,200 @@
+// The Tucker operator over the complex field and its conjugate-transpose
+// form (Sec. 2 states the mu-mode product and the Tucker operator for complex
+// tensors; Sec. 3 applies the conjugate-transposed basis matrices to evaluate
+// spectral decompositions at their quadrature grid).
+//
+// A complex tensor is stored as interleaved (real, imaginary) pairs, i.e. as
+// a real tensor with an extra first mode of size 2; the real and imaginary
+// parts of a factor are two real matrices (two strided views of an
+// interleaved complex matrix). Mode mu of the complex product is then
+//   Y = X x_(mu+1) Re(L) + i s (X x_(mu+1) Im(L)),
+// two real mu-mode products on the same real kernels (the size-2 mode sits
+// in the fibers' leading index) and one element-wise pass that adds i s B,
+// s = +1 for L and -1 for the conjugate transpose.
+#include "kp.h"
+
+#include "kp_common.h"
+#include "kp_internal.h"
+
+namespace kp {
+namespace {
+
+constexpr int kCT = 256;
+
+// y += i s b for `count` complex values stored as (re, im) pairs.
+template <typename E>
+__global__ __launch_bounds__(kCT) void add_i_times_kernel(E* __restrict__ y,
+                                                          const E* __restrict__ b,
+                                                          int64_t count, E s) {
+  for (int64_t e = blockIdx.x * static_cast<int64_t>(kCT) + threadIdx.x; e < count;
+       e += static_cast<int64_t>(gridDim.x) * kCT) {
+    const E br = b[2 * e], bi = b[2 * e + 1];
+    const E yr = y[2 * e], yi = y[2 * e + 1];
+    y[2 * e] = yr - s * bi;
+    y[2 * e + 1] = yi + s * br;
+  }
+}
+
+int64_t count_of(const int64_t* dims, int d) {
+  int64_t s = 1;
+  for (int k = 0; k < d; ++k) s *= dims[k];
+  return s;
+}
+
+// The factor applied at complex mode k: L, or its transpose for the
+// conjugate-transpose form (the sign of the imaginary part is applied by
+// the combining pass).
+kp_matrix applied(const kp_matrix& L, int conj) {
+  if (!conj) return L;
+  kp_matrix t = L;
+  t.rows = L.cols;
+  t.cols = L.rows;
+  t.rs = L.cs;
+  t.cs = L.rs;
+  return t;
+}
+
+struct ComplexPlan {
+  int d;                                    // complex order
+  int64_t dims[KP_MAX_ORDER + 1][KP_MAX_ORDER];  // real dims before step s
+  int steps;
+  int mode[KP_MAX_ORDER];                   // complex mode (0-based) of step s
+  int64_t big;                              // largest intermediate (real entries)
+  int64_t bigb;                             // largest product output (real entries)
+};
+
+int validate(const kp_tensor* T, const kp_matrix* const* Lre, const kp_matrix* const* Lim,
+             int conj, int prec, ComplexPlan* p) {
+  int st = check_tensor(T, true);
+  if (st) return st;
+  if (!Lre || !Lim) return KP_ERR_NULL;
+  if (T->d < 2) return KP_ERR_ORDER;
+  if (T->dims[0] != 2) return KP_ERR_SHAPE;
+  st = check_prec(prec, T->dtype);
+  if (st) return st;
+  p->d = T->d - 1;
+  p->steps = 0;
+  p->big = 0;
+  p->bigb = 0;
+  int64_t cur[KP_MAX_ORDER];
+  for (int k = 0; k < T->d; ++k) cur[k] = T->dims[k];
+  for (int k = 0; k < p->d; ++k) {
+    if (!Lre[k]) {
+      if (Lim[k]) return KP_ERR_NULL;
+      continue;
+    }
+    st = check_matrix(Lre[k], T->dtype);
+    if (st) return st;
+    const kp_matrix a = applied(*Lre[k], conj);
+    if (a.cols != T->dims[k + 1]) return KP_ERR_SHAPE;
+    if (Lim[k]) {
+      st = check_matrix(Lim[k], T->dtype);
+      if (st) return st;
+      if (Lim[k]->rows != Lre[k]->rows || Lim[k]->cols != Lre[k]->cols) return KP_ERR_SHAPE;
+    }
+    for (int j = 0; j < T->d; ++j) p->dims[p->steps][j] = cur[j];
+    p->mode[p->steps] = k;
+    cur[k + 1] = a.rows;
+    const int64_t out = count_of(cur, T->d);
+    if (Lim[k] && out > p->bigb) p->bigb = out;
+    ++p->steps;
+    if (out > p->big) p->big = out;
+  }
+  for (int j = 0; j < T->d; ++j) p->dims[p->steps][j] = cur[j];
+  return KP_OK;
+}
+
+}  // namespace
+}  // namespace kp
+
+using namespace kp;
+
+extern "C" {
+
+size_t kp_tucker_complex_workspace(const kp_tensor* T, const kp_matrix* const* Lre,
+                                   const kp_matrix* const* Lim, int conj, int prec) {
+  ComplexPlan p;
+  if (validate(T, Lre, Lim, conj, prec, &p)) return 0;
+  const size_t es = elem_size(T->dtype);
+  // two ping-pong buffers for the intermediates (only with two or more
+  // steps) and one for the imaginary-part products
+  const size_t inter = p.steps > 1 ? 2 * align_up(static_cast<size_t>(p.big) * es) : 0;
+  return inter + align_up(static_cast<size_t>(p.bigb) * es);
+}
+
+int kp_tucker_complex(const kp_tensor* T, const kp_matrix* const* Lre,
+                      const kp_matrix* const* Lim, kp_tensor* S, int conj, int prec, void* ws,
+                      size_t ws_bytes, hipStream_t stream) {
+  ComplexPlan p;
+  int st = validate(T, Lre, Lim, conj, prec, &p);
+  if (st) return st;
+  if (!S) return KP_ERR_NULL;
+  st = check_tensor(S, true);
+  if (st) return st;
+  if (S->dtype != T->dtype) return KP_ERR_DTYPE;
+  if (S->d != T->d) return KP_ERR_SHAPE;
+  for (int j = 0; j < T->d; ++j)
+    if (S->dims[j] != p.dims[p.steps][j]) return KP_ERR_SHAPE;
+  const size_t es = elem_size(T->dtype);
+  const size_t sb = static_cast<size_t>(numel(*S)) * es;
+  const size_t tb = static_cast<size_t>(numel(*T)) * es;
+  if (overlaps(S->data, sb, T->data, tb)) return KP_ERR_ALIAS;
+  for (int k = 0; k < p.d; ++k) {
+    if (Lre[k] && overlaps(S->data, sb, Lre[k]->data, matrix_span_bytes(*Lre[k])))
+      return KP_ERR_ALIAS;
+    if (Lim[k] && overlaps(S->data, sb, Lim[k]->data, matrix_span_bytes(*Lim[k])))
+      return KP_ERR_ALIAS;
+  }
+  const size_t need = kp_tucker_complex_workspace(T, Lre, Lim, conj, prec);
+  if (need > 0 && (!ws || ws_bytes < need)) return KP_ERR_WORKSPACE;
+  if (need > 0 && (overlaps(ws, need, S->data, sb) || overlaps(ws, need, T->data, tb)))
+    return KP_ERR_ALIAS;
+  if (numel(*S) == 0) return KP_OK;
+  if (p.steps == 0)
+    return hip_status(hipMemcpyAsync(S->data, T->data, sb, hipMemcpyDeviceToDevice, stream));
+
+  const int form = form_of(prec, T->dtype);
+  char* w = static_cast<char*>(ws);
+  const size_t buf = align_up(static_cast<size_t>(p.big) * es);
+  char* pp[2] = {w, w + buf};
+  char* bbuf = w + (p.steps > 1 ? 2 * buf : 0);
+  const void* src = T->data;
+  int cur = -1;
+  for (int s = 0; s < p.steps; ++s) {
+    const int k = p.mode[s];
+    void* dst;
+    if (s == p.steps - 1) {
+      dst = S->data;
+    } else {
+      cur = cur == 0 ? 1 : 0;
+      dst = pp[cur];
+    }
+    const kp_matrix re = applied(*Lre[k], conj);
+    ModeArgs a = mode_args(src, dst, p.dims[s], T->d, k + 1, re, 0);
+    st = hip_status(launch_mode(form, a, tile_override(), stream));
+    if (st) return st;
+    if (Lim[k]) {
+      const kp_matrix im = applied(*Lim[k], conj);
+      ModeArgs b = mode_args(src, bbuf, p.dims[s], T->d, k + 1, im, 0);
+      st = hip_status(launch_mode(form, b, tile_override(), stream));
+      if (st) return st;
+      const int64_t count = count_of(p.dims[s + 1], T->d) / 2;
+      const int64_t blocks = (count + kCT - 1) / kCT;
+      const unsigned grid = static_cast<unsigned>(blocks < 4096 ? blocks : 4096);
+      if (T->dtype == KP_F64)
+        hipLaunchKernelGGL(add_i_times_kernel<double>, dim3(grid), dim3(kCT), 0, stream,
+                           static_cast<double*>(dst), reinterpret_cast<const double*>(bbuf),
+                           count, conj ? -1.0 : 1.0);
+      else
+        hipLaunchKernelGGL(add_i_times_kernel<float>, dim3(grid), dim3(kCT), 0, stream,
+                           static_cast<float*>(dst), reinterpret_cast<const float*>(bbuf),
+                           count, conj ? -1.0f : 1.0f);
+      st = hip_status(hipGetLastError());
+      if (st) return st;
+    }
+    src = dst;
+  }
+  return KP_OK;
+}
+
+}  // extern "C"

@@ -20,6 +20,9 @@ size_t elem_size(int dtype);
 size_t align_up(size_t x);
 // Argument checks shared by the entry points (kp_api.hip): KP_OK or an error.
 int check_tensor(const kp_tensor* t, bool need_data);
+int check_prec(int prec, int dtype);
+int form_of(int prec, int dtype);
+int64_t numel(const kp_tensor& t);
 int check_matrix(const kp_matrix* L, int dtype);
 bool overlaps(const void* a, size_t abytes, const void* b, size_t bbytes);
 size_t matrix_span_bytes(const kp_matrix& L);

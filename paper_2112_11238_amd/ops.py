@@ -271,6 +271,56 @@ def expm(A, tau=1.0):
     return E if batched else E[0]
 
 
+def tucker_complex(T, Ls, conj=False, prec="native"):
+    """Complex Tucker operator S = T x_1 L_1 ... x_d L_d (conj: the conjugate
+    transposes L_mu^*, each L_mu then m_mu x n_mu) for complex128 / complex64
+    T; a factor may be complex, real (same real dtype) or None (identity).
+    Zero-copy: the interleaved storage is passed as real views
+    (kp_tucker_complex)."""
+    _check_device(T, *Ls)
+    if T.dtype not in (torch.complex128, torch.complex64):
+        raise TypeError("tucker_complex expects a complex128 or complex64 tensor")
+    d = T.dim()
+    if len(Ls) != d:
+        raise ValueError(f"need {d} factors, got {len(Ls)}")
+    rdt = torch.float64 if T.dtype == torch.complex128 else torch.float32
+    Tr = torch.view_as_real(T.contiguous())            # (m_1..m_d, 2): (2, m_d..m_1) canonical
+    res, ims = [], []
+    for L in Ls:
+        if L is None:
+            res.append(None)
+            ims.append(None)
+        elif L.is_complex():
+            if L.dtype != T.dtype:
+                raise TypeError("complex factors must share T's dtype")
+            Lv = torch.view_as_real(L)                 # (rows, cols, 2), any strides
+            res.append(_mdesc(Lv[..., 0]))
+            ims.append(_mdesc(Lv[..., 1]))
+        else:
+            if L.dtype != rdt:
+                raise TypeError("real factors must have T's real dtype")
+            res.append(_mdesc(L))
+            ims.append(None)
+    shape = []
+    for k in range(d):
+        if Ls[k] is None:
+            shape.append(T.shape[k])
+        else:
+            shape.append(Ls[k].shape[1] if conj else Ls[k].shape[0])
+    S = torch.empty(shape, dtype=T.dtype, device=T.device)
+    Sr = torch.view_as_real(S)
+    td, sd = _tdesc(Tr, True), _tdesc(Sr, True)
+    rarr, iarr = _mlist(res[::-1]), _mlist(ims[::-1])
+    lb = lib()
+    c = 1 if conj else 0
+    ws_bytes = lb.kp_tucker_complex_workspace(ctypes.byref(td), rarr, iarr, c, _prec(prec))
+    ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=T.device)
+    st = lb.kp_tucker_complex(ctypes.byref(td), rarr, iarr, ctypes.byref(sd), c, _prec(prec),
+                              ws.data_ptr(), ws_bytes, _stream())
+    check(st, "kp_tucker_complex")
+    return S
+
+
 def _f64_device(*ts):
     _check_device(*ts)
     for t in ts:

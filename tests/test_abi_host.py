@@ -232,6 +232,30 @@ def test_expm_argument_errors(lib):
 
 
 @no_device
+def test_tucker_complex_argument_errors(lib, L):
+    T = tensor(L, [2, 4, 5])
+    S = tensor(L, [2, 3, 6], data=FAKE + 0x200000)
+    Re = [matrix(L, 3, 4, data=FAKE + 0x400000), matrix(L, 6, 5, data=FAKE + 0x401000)]
+    Im = [matrix(L, 3, 4, data=FAKE + 0x402000), None]
+    ws = FAKE + 0x800000
+    wsb = lib.kp_tucker_complex_workspace(ctypes.byref(T), mlist(L, Re), mlist(L, Im), 0, 0)
+    assert wsb > 0
+
+    def call(t=T, re=Re, im=Im, s=S, conj=0, prec=0, w=ws, nb=wsb):
+        return lib.kp_tucker_complex(ctypes.byref(t), mlist(L, re), mlist(L, im),
+                                     ctypes.byref(s), conj, prec, w, nb, None)
+    assert call(t=tensor(L, [3, 4, 5])) == -4                       # first mode not 2
+    assert call(t=tensor(L, [2])) == -2                             # no complex mode
+    assert call(re=[None, Re[1]]) == -1                             # imaginary part alone
+    assert call(im=[matrix(L, 3, 5), None]) == -4                   # parts differ in size
+    assert call(s=tensor(L, [2, 3, 7], data=FAKE + 0x200000)) == -4
+    assert call(conj=1) == -4                                       # L^* would be 4 x 3
+    assert call(prec=3) == -5
+    assert call(nb=wsb - 1) == -7
+    assert call(s=tensor(L, [2, 3, 6], data=FAKE + 8)) == -6
+
+
+@no_device
 def test_tridiag_inverse_argument_errors(lib):
     f = lib.kp_tridiag_inverse_f64
     lo, dg, up, E = FAKE, FAKE + 0x1000, FAKE + 0x2000, FAKE + 0x100000

@@ -1,0 +1,104 @@
+"""Complex Tucker operator and its conjugate-transpose form on the device
+(Sec. 2 over C; Sec. 3 spectral transforms) against the oracle and numpy's
+FFT, in every form."""
+import numpy as np
+import pytest
+import torch
+
+import kp_workloads
+import oracle
+from gpu_util import say, unit_error
+
+pytestmark = pytest.mark.gpu
+
+FORMS = [("c128", "native"), ("c64", "native"), ("c64", "bf16x3"), ("c64", "bf16x6")]
+CDT = {"c128": torch.complex128, "c64": torch.complex64}
+RDT = {"c128": torch.float64, "c64": torch.float32}
+CASES = [((7, 5), (4, 9)), ((19, 45, 13), (7, 70, 29)), ((30, 3, 70), (2, 33, 64)),
+         ((5, 6, 4, 3), (3, 7, 2, 5))]
+
+
+@pytest.fixture(scope="module")
+def kp():
+    import paper_2112_11238_amd as kp
+    return kp
+
+
+def dev(x, cdt):
+    return torch.as_tensor(np.ascontiguousarray(x)).to(device="cuda", dtype=cdt)
+
+
+def seen(x, cdt):
+    """The values the device sees, back in complex128."""
+    return torch.as_tensor(x).to(cdt).to(torch.complex128).numpy()
+
+
+def bound(T, Ls, conj, prec, rdt, safety=2.0):
+    """Componentwise bound for either part of S: the real Tucker operator on
+    |Re| + |Im| of T and of each factor, times the summed per-mode error
+    coefficients (two real products of length m and the combining add)."""
+    absT = np.abs(T.real) + np.abs(T.imag)
+    absL = []
+    for L in Ls:
+        a = np.abs(L.real) + np.abs(L.imag)
+        absL.append(a.T if conj else a)
+    u = 2.0 ** -53 if rdt == torch.float64 else 2.0 ** -24
+    coef = sum(unit_error(prec, rdt, 2 * T.shape[k]) + 2 * u for k in range(T.ndim))
+    return safety * coef * oracle.tucker(absT, absL) + 1e-300
+
+
+@pytest.mark.parametrize("form,prec", FORMS)
+@pytest.mark.parametrize("case", range(len(CASES)))
+@pytest.mark.parametrize("conj", [False, True])
+def test_tucker_complex_matches_oracle(kp, form, prec, case, conj):
+    m, n = CASES[case]
+    T, Ls = kp_workloads.complex_problem(500 + case, m, n, conj)
+    say("complex tucker", m, n, form, prec, "conj" if conj else "")
+    S = kp.tucker_complex(dev(T, CDT[form]), [dev(L, CDT[form]) for L in Ls], conj=conj,
+                          prec=prec)
+    torch.cuda.synchronize()
+    T64, L64 = seen(T, CDT[form]), [seen(L, CDT[form]) for L in Ls]
+    ref = oracle.cttucker(T64, L64) if conj else oracle.ztucker(T64, L64)
+    got = S.to(torch.complex128).cpu().numpy()
+    assert got.shape == ref.shape
+    b = bound(T64, L64, conj, prec, RDT[form])
+    assert np.all(np.abs(got.real - ref.real) <= b)
+    assert np.all(np.abs(got.imag - ref.imag) <= b)
+
+
+def test_fourier_transform_and_inverse(kp):
+    shape = (64, 48, 30)
+    rng = np.random.default_rng(9)
+    T = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    Fs = [dev(kp_workloads.fourier_matrix(k), torch.complex128) for k in shape]
+    say("fourier", shape)
+    S = kp.tucker_complex(dev(T, torch.complex128), Fs)
+    back = kp.tucker_complex(S, Fs, conj=True)
+    torch.cuda.synchronize()
+    ref = np.fft.fftn(T)
+    got = S.cpu().numpy()
+    assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+    inv = back.cpu().numpy() / T.size
+    assert np.max(np.abs(inv - T)) <= 1e-12 * np.max(np.abs(T))
+
+
+@pytest.mark.parametrize("form", ["c128", "c64"])
+def test_identity_and_real_factors(kp, form):
+    rng = np.random.default_rng(10)
+    T = rng.standard_normal((6, 5, 7)) + 1j * rng.standard_normal((6, 5, 7))
+    Lr = rng.standard_normal((4, 5))
+    Lc = rng.standard_normal((3, 7)) + 1j * rng.standard_normal((3, 7))
+    rdt = RDT[form]
+    say("complex mixed factors", form)
+    S = kp.tucker_complex(dev(T, CDT[form]),
+                          [None, torch.as_tensor(Lr).to(device="cuda", dtype=rdt),
+                           dev(Lc, CDT[form])])
+    same = kp.tucker_complex(dev(T, CDT[form]), [None, None, None])
+    torch.cuda.synchronize()
+    T64 = seen(T, CDT[form])
+    L64 = [None, torch.as_tensor(Lr).to(rdt).double().numpy(), seen(Lc, CDT[form])]
+    ref = oracle.ztucker(T64, L64)
+    b = bound(T64, [np.eye(6), L64[1], L64[2]], False, "native", rdt)
+    got = S.to(torch.complex128).cpu().numpy()
+    assert np.all(np.abs(got.real - ref.real) <= b) and np.all(np.abs(got.imag - ref.imag) <= b)
+    assert torch.equal(same, dev(T, CDT[form]))
