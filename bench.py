@@ -58,7 +58,7 @@ def parse():
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--workload", default="cube200",
                     choices=["cube200", "small2d", "heat128", "interp6d", "batch64", "semilinear",
-                             "runge5d", "codeval"],
+                             "runge5d", "codeval", "fft3d"],
                     help="cube200 is the headline line; the others time the remaining "
                          "configurations (one JSON line each)")
     ap.add_argument("--autotune", action="store_true",
@@ -675,6 +675,66 @@ def bench_codeval(args):
                               "d=3 n in {144,196,256,324}, d=6 n in {12,14,16,18}"}, extra)
 
 
+def bench_fft3d(args):
+    """A 3-D discrete Fourier transform of a complex 200^3 tensor as a
+    complex Tucker operator with Fourier matrices, and its inverse through
+    the conjugate-transpose form, in complex128 and complex64 (and the BF16
+    splits on complex64). Real flops: 8 n m per complex output of each mode."""
+    import torch
+
+    import paper_2112_11238_amd as kp
+    n = 200
+    rng = np.random.default_rng(0)
+    T = rng.standard_normal((n,) * 3) + 1j * rng.standard_normal((n,) * 3)
+    F = kp_workloads.fourier_matrix(n)
+    ref = np.fft.fftn(T)
+    rmax = float(np.abs(ref).max())
+    flops = 3 * 8 * n ** 4
+    forms = {}
+    for name, cdt, prec in [("c128", torch.complex128, "native"), ("c64", torch.complex64, "native"),
+                            ("c64_bf16x3", torch.complex64, "bf16x3"),
+                            ("c64_bf16x6", torch.complex64, "bf16x6")]:
+        if args.forms != "all" and name.split("_")[-1] not in args.forms.split(",") and \
+                name not in args.forms.split(","):
+            continue
+        Td = torch.tensor(T, dtype=cdt, device="cuda")
+        Fd = [torch.tensor(F, dtype=cdt, device="cuda")] * 3
+        S = kp.tucker_complex(Td, Fd, prec=prec)
+        back = kp.tucker_complex(S, Fd, conj=True, prec=prec)
+        torch.cuda.synchronize()
+        err = float(np.abs(S.to(torch.complex128).cpu().numpy() - ref).max() / rmax)
+        inv = float(np.abs(back.to(torch.complex128).cpu().numpy() / T.size - T).max()
+                    / np.abs(T).max())
+        ms = _events_ms(lambda: kp.tucker_complex(Td, Fd, prec=prec), args.steps, args.warmup)
+        ims = _events_ms(lambda: kp.tucker_complex(S, Fd, conj=True, prec=prec), args.steps,
+                         args.warmup)
+        forms[name] = {"ms_forward": round(ms, 4), "tflops": round(flops / (ms * 1e-3) / 1e12, 3),
+                       "ms_inverse": round(ims, 4), "rel_err_vs_numpy_fft": err,
+                       "inverse_rel_err": inv}
+        del Td, S, back
+        torch.cuda.empty_cache()
+    head = forms.get("c128") or next(iter(forms.values()))
+    extra = {"forms": forms}
+    if not args.no_cpu_baseline:
+        import oracle
+        t0 = time.perf_counter()
+        reps = 0
+        while reps < 3 or time.perf_counter() - t0 < 5.0:
+            oracle.ztucker(T, [F] * 3)
+            reps += 1
+        sec = (time.perf_counter() - t0) / reps
+        extra["cpu_baseline"] = {"value": round(flops / sec / 1e12, 6),
+                                 "unit": "TFLOP/s", "cores": _threads(), "kind": "oracle",
+                                 "sample": f"{reps} oracle complex Tucker calls on the same "
+                                           f"input ({sec:.3f} s each)"}
+    return _line(args, "complex Tucker-op TFLOP/s fft3d (d=3, n=200, Fourier factors, complex128)",
+                 head["tflops"], "TFLOP/s", head["ms_forward"], "c128",
+                 {"workload": "fft3d: complex 200^3 tensor, real and imaginary parts N(0,1) "
+                              "seed 0, Fourier matrices per mode; forward transform timed, the "
+                              "inverse through the conjugate-transpose form",
+                  "flops_per_step": flops}, extra)
+
+
 def bench_semilinear(args):
     """The semilinear experiment (n = (40, 44, 48), tau = 0.01, 100 steps to
     t = 1): ADI factor inverses built on the device, one PCG solve per step
@@ -757,7 +817,7 @@ def bench_semilinear(args):
 WORKLOAD_BENCHES = {"small2d": bench_small2d, "heat128": bench_heat128,
                     "interp6d": bench_interp6d, "batch64": bench_batch64,
                     "semilinear": bench_semilinear, "runge5d": bench_runge5d,
-                    "codeval": bench_codeval}
+                    "codeval": bench_codeval, "fft3d": bench_fft3d}
 
 
 if __name__ == "__main__":
