@@ -115,10 +115,11 @@ const Variant* find_variant(int form, const ModeTile& t) {
 // footprint: 4 waves/SIMD), with two chunks of loads in flight once m >= 256;
 // FP32 7 blocks (8 at n <= 128) with two chunks of loads in flight; the
 // BF16 split forms 4 blocks (BF16x6 with two chunks in flight). Short
-// contractions (m <= 64) take strip tiles.
-ModeTile pick_tile(int form, int64_t m, int64_t n) {
+// contractions (m <= 64; FP64: m <= 32, or m <= 64 on the lead layout)
+// take strip tiles.
+ModeTile pick_tile(int form, int64_t Il, int64_t m, int64_t n) {
   ModeTile t{};
-  if (strip_default(form, m, n, &t)) return t;
+  if (strip_default(form, Il, m, n, &t)) return t;
   t.occ = 0;
   t.pf = 0;
   if (form == FORM_F64) {
@@ -153,12 +154,14 @@ ModeTile pick_tile(int form, int64_t m, int64_t n) {
 
 }  // namespace
 
-ModeTile builtin_mode_tile(int form, int64_t m, int64_t n) { return pick_tile(form, m, n); }
+ModeTile builtin_mode_tile(int form, int64_t Il, int64_t m, int64_t n) {
+  return pick_tile(form, Il, m, n);
+}
 
 ModeTile default_mode_tile(int form, const ModeArgs& a) {
   ModeTile t;
   if (tuned_tile(form, a.Il, a.m, a.n, a.Ir, &t)) return t;
-  return pick_tile(form, a.m, a.n);
+  return pick_tile(form, a.Il, a.m, a.n);
 }
 
 bool resolve_mode_tile(int form, const ModeTile& t, ModeTile* out) {

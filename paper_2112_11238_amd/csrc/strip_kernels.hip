@@ -32,13 +32,16 @@ struct StripVariant {
    strip_kernel<FORM, NB, FB, KP, false, false>, strip_kernel<FORM, NB, FB, KP, false, true>}
 
 // Fiber blocks per wave chosen per (form, KP) so that a workgroup's LDS
-// (L block plus two fiber tiles) stays near 56 KB or less.
+// (L block plus two fiber tiles) stays near 56 KB or less, except the FP64
+// strips of 48 and 64 (58-101 KB: one or two workgroups per CU).
 const StripVariant kStrips[] = {
     KP_S(FORM_F32, 1, 2, 16), KP_S(FORM_F32, 2, 2, 16), KP_S(FORM_F32, 4, 2, 16),
     KP_S(FORM_F32, 1, 2, 32), KP_S(FORM_F32, 2, 2, 32), KP_S(FORM_F32, 4, 2, 32),
     KP_S(FORM_F32, 1, 1, 64), KP_S(FORM_F32, 2, 1, 64), KP_S(FORM_F32, 4, 1, 64),
     KP_S(FORM_F64, 1, 2, 16), KP_S(FORM_F64, 2, 2, 16), KP_S(FORM_F64, 4, 2, 16),
     KP_S(FORM_F64, 1, 1, 32), KP_S(FORM_F64, 2, 1, 32), KP_S(FORM_F64, 4, 1, 32),
+    KP_S(FORM_F64, 1, 1, 48), KP_S(FORM_F64, 2, 1, 48), KP_S(FORM_F64, 4, 1, 48),
+    KP_S(FORM_F64, 1, 1, 64), KP_S(FORM_F64, 2, 1, 64), KP_S(FORM_F64, 4, 1, 64),
     KP_S(FORM_BF16X3, 1, 2, 32), KP_S(FORM_BF16X3, 2, 2, 32), KP_S(FORM_BF16X3, 4, 2, 32),
     KP_S(FORM_BF16X3, 1, 1, 64), KP_S(FORM_BF16X3, 2, 1, 64), KP_S(FORM_BF16X3, 4, 1, 64),
     KP_S(FORM_BF16X6, 1, 1, 32), KP_S(FORM_BF16X6, 2, 1, 32), KP_S(FORM_BF16X6, 4, 1, 32),
@@ -52,7 +55,7 @@ const StripVariant* find_strip(int form, const ModeTile& t) {
   return nullptr;
 }
 
-int max_strip(int form) { return form == FORM_F64 ? 32 : 64; }
+int max_strip(int) { return 64; }
 
 // Resident workgroups per CU of a kernel (queried once per kernel).
 int blocks_per_cu(StripFn fn) {
@@ -81,13 +84,17 @@ int device_cus() {
 
 }  // namespace
 
-bool strip_default(int form, int64_t m, int64_t n, ModeTile* out) {
+bool strip_default(int form, int64_t Il, int64_t m, int64_t n, ModeTile* out) {
   if (m < 1 || m > max_strip(form)) return false;
+  // FP64 with 32 < m <= 64: the 48- and 64-long strips (one or two
+  // workgroups per CU) beat the k-loop tile on the lead layout only
+  if (form == FORM_F64 && m > 32 && Il > 1) return false;
   // FP32 with m <= 16: the k-loop tile (one chunk, 16-byte loads) measured
   // faster than the strip
   if (form == FORM_F32 && m <= 16) return false;
-  const int kp = form == FORM_BF16X3 || form == FORM_BF16X6 ? (m <= 32 ? 32 : 64)
-                                                             : (m <= 16 ? 16 : (m <= 32 ? 32 : 64));
+  const int kp = form == FORM_BF16X3 || form == FORM_BF16X6
+                     ? (m <= 32 ? 32 : 64)
+                     : (m <= 16 ? 16 : (m <= 32 ? 32 : (form == FORM_F64 && m <= 48 ? 48 : 64)));
   const int nb = n <= 16 ? 1 : (n <= 32 ? 2 : 4);
   ModeTile t{nb, 0, kp, 0, 0, 1};
   return strip_resolve(form, t, out);

@@ -54,7 +54,8 @@ def test_variant_lists(lib, tune):
             assert any(w[:3] == v[:3] and w[5] == v[5] for w in mode), (form, v)
         # strip tiles (kind 1): occ = pf = 0, bk the padded contraction length
         strips = [v for v in mode if v[5] == 1]
-        assert strips and all(v[3:5] == (0, 0) and v[2] in (16, 32, 64) for v in strips)
+        assert strips and all(v[3:5] == (0, 0) and v[2] in (16, 32, 48, 64) for v in strips)
+        assert any(v[2] == 48 for v in strips) == (form == 0)      # FP64 only
         assert all(v[5] == 0 or v[2] >= 40 for v in tune.variants(form, m=40))
         assert len(tune.variants(form, m=200)) == len(mode) - len(strips)
     assert lib.kp_tile_variants(2, 0, None, 0) == -9
@@ -82,6 +83,10 @@ def test_set_lookup_list_clear(lib, L, tune):
     assert not tuned and tile[:3] == (7, 1, 8)
     # long FP64 contractions keep two chunks of loads in flight
     assert tune.lookup("f64", 1, 324, 324, 324 * 324) == (False, (7, 1, 8, 2, 2, 0))
+    # FP64 with 32 < m <= 64: a strip on the lead layout, the k-loop tile inside
+    assert tune.lookup("f64", 1, 45, 35, 1000) == (False, (4, 1, 48, 0, 0, 1))
+    assert tune.lookup("f64", 1, 60, 64, 1000) == (False, (4, 1, 64, 0, 0, 1))
+    assert tune.lookup("f64", 35, 45, 35, 1000)[1][5] == 0
     tune.set_tile("f64", 40, 200, 200, 200, (4, 1, 16))
     tuned, tile = tune.lookup("f64", 40, 200, 200, 200)
     assert tuned and tile[:3] == (4, 1, 16) and tile[3] > 0 and tile[4:] == (1, 0)  # resolved
