@@ -25,8 +25,8 @@ constexpr int kThreads = 256;  // threads per workgroup (4 waves)
 //     B[8(l/16) .. +7][l%16]; item v of lane l is D[4(l/16) + v][l%16].
 // ---------------------------------------------------------------------------
 // Offset of fiber r = a + Il*b of a (Il, len, Ir) view: a + Il*len*b.
-__device__ __forceinline__ int64_t fiber_offset(int64_t r, int64_t Il, int64_t len) {
-  const int64_t b = r / Il;
+__device__ __forceinline__ uint32_t fiber_offset(uint32_t r, uint32_t Il, uint32_t len) {
+  const uint32_t b = r / Il;
   return (r - b * Il) + Il * len * b;
 }
 
@@ -215,38 +215,48 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t bx, int64_t
   // or columns that are never stored. Only the k tail needs zeros.
   uint32_t xo[XT][KV], lo_[LT][KV];
   int xkg[XT], lkg[LT];
-  const int64_t xkstep = INNER ? Il : 1;  // elements per unit of k in X
+  // 32-bit index math: every element offset of X, Y and the span of L are
+  // below 2^31 bytes (the host splits launches and checks factor spans)
+  const uint32_t Il32 = static_cast<uint32_t>(Il), m32 = static_cast<uint32_t>(m);
+  const uint32_t n32 = static_cast<uint32_t>(n), F32 = static_cast<uint32_t>(F);
+  const uint32_t f032 = static_cast<uint32_t>(f0), i032 = static_cast<uint32_t>(i0);
+  const uint32_t xkstep = INNER ? Il32 : 1;  // elements per unit of k in X
 #pragma unroll
   for (int s = 0; s < XT; ++s) {
     const int id = t + s * kThreads;
-    int64_t rowoff;
+    uint32_t rowoff;
     int kg;
     if (INNER) {
       kg = (id / BF) % KG;
-      int64_t r = f0 + id % BF;
-      r = r < F ? r : F - 1;
-      rowoff = fiber_offset(r, Il, m);
+      uint32_t r = f032 + id % BF;
+      r = r < F32 ? r : F32 - 1;
+      rowoff = fiber_offset(r, Il32, m32);
     } else {
       kg = id % KG;
-      int64_t f = f0 + (id / KG) % BF;
-      f = f < F ? f : F - 1;
-      rowoff = f * m;
+      uint32_t f = f032 + (id / KG) % BF;
+      f = f < F32 ? f : F32 - 1;
+      rowoff = f * m32;
     }
     xkg[s] = kg;
 #pragma unroll
     for (int e = 0; e < KV; ++e)
-      xo[s][e] = static_cast<uint32_t>((rowoff + (kg * KV + e) * xkstep) * sizeof(G));
+      xo[s][e] = (rowoff + static_cast<uint32_t>(kg * KV + e) * xkstep) *
+                 static_cast<uint32_t>(sizeof(G));
   }
+  const uint32_t rs32 = static_cast<uint32_t>(a.rs), cs32 = static_cast<uint32_t>(a.cs);
 #pragma unroll
   for (int s = 0; s < LT; ++s) {
     const int id = t + s * kThreads;
     const int kg = id % KG;
-    int64_t i = i0 + (id / KG) % BN;
-    i = i < n ? i : n - 1;
+    uint32_t i = i032 + (id / KG) % BN;
+    i = i < n32 ? i : n32 - 1;
     lkg[s] = kg;
+    // offsets of k past m (tail chunk only) may wrap; they are replaced by
+    // an out-of-range offset before use
 #pragma unroll
     for (int e = 0; e < KV; ++e)
-      lo_[s][e] = static_cast<uint32_t>((i * a.rs + (kg * KV + e) * a.cs) * sizeof(G));
+      lo_[s][e] = (i * rs32 + static_cast<uint32_t>(kg * KV + e) * cs32) *
+                  static_cast<uint32_t>(sizeof(G));
   }
   static_assert(PF == 1 || PF == 2, "prefetch distance 1 or 2");
   G xr[PF][XT][KV], lr[PF][LT][KV];
@@ -462,35 +472,40 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t bx, int64_t
   }
 
   // Store: MFMA column = lane & 15 is the memory-contiguous output index.
+  // Through a buffer resource over Y: rows past n and fibers past F get an
+  // offset past the resource, and the hardware drops the store.
+  constexpr uint32_t kDrop = 0x80000000u;  // >= any resource size here
+  const auto yrs = __builtin_amdgcn_make_buffer_rsrc(
+      Y, 0, static_cast<int>(a.Il * a.n * a.Ir * sizeof(G)), kBufferFlags);
+  constexpr uint32_t ES = static_cast<uint32_t>(sizeof(G));
 #pragma unroll
   for (int q = 0; q < QB; ++q)
 #pragma unroll
     for (int p = 0; p < PB; ++p) {
       acc_t val = hi[q][p];
       if constexpr (SPLIT) val = hi[q][p] + lo[q][p];
-      if (INNER) {
-        const int64_t r = f0 + w * 16 * FB + p * 16 + c;
-        if (r >= F) continue;
-        G* yb = Y + fiber_offset(r, Il, n);
+      uint32_t off[4];
+      if constexpr (INNER) {
+        const uint32_t r = f032 + w * 16 * FB + p * 16 + c;
+        const uint32_t yb = fiber_offset(r < F32 ? r : 0, Il32, n32);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int64_t i = i0 + q * 16 + FT::row(lane, v);
-          if (i < n) {
-            G* dst = yb + Il * i;
-            *dst = a.accumulate ? *dst + val[v] : val[v];
-          }
+          const uint32_t i = i032 + q * 16 + FT::row(lane, v);
+          off[v] = (r < F32 && i < n32) ? (yb + Il32 * i) * ES : kDrop;
         }
       } else {
-        const int64_t i = i0 + p * 16 + c;
-        if (i >= n) continue;
+        const uint32_t i = i032 + p * 16 + c;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int64_t f = f0 + w * 16 * FB + q * 16 + FT::row(lane, v);
-          if (f < F) {
-            G* dst = Y + i + n * f;
-            *dst = a.accumulate ? *dst + val[v] : val[v];
-          }
+          const uint32_t f = f032 + w * 16 * FB + q * 16 + FT::row(lane, v);
+          off[v] = (f < F32 && i < n32) ? (i + n32 * f) * ES : kDrop;
         }
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        G y = val[v];
+        if (a.accumulate) y += buffer_load<G>(yrs, off[v]);
+        buffer_store<G>(y, yrs, off[v]);
       }
     }
 }
