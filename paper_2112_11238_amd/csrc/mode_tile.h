@@ -43,6 +43,26 @@ __device__ __forceinline__ void split_bf16(float x, __bf16 (&o)[P]) {
   }
 }
 
+// The same split for KV consecutive values at once, two per conversion
+// (each pair of bf16 terms is one round-to-nearest-even packed conversion),
+// written as the P bf16 planes of one k group.
+template <int P, int KV, typename V8>
+__device__ __forceinline__ void split_bf16_group(const float (&x)[KV], V8 (&pl)[P]) {
+  typedef float f2 __attribute__((ext_vector_type(2)));
+  typedef __bf16 b2 __attribute__((ext_vector_type(2)));
+#pragma unroll
+  for (int e = 0; e < KV; e += 2) {
+    f2 r = {x[e], x[e + 1]};
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const b2 h = __builtin_convertvector(r, b2);
+      pl[p][e] = h[0];
+      pl[p][e + 1] = h[1];
+      if (p + 1 < P) r = r - __builtin_convertvector(h, f2);
+    }
+  }
+}
+
 // Buffer resource word 3 for raw (unformatted, unswizzled) buffers on the
 // gfx9 family; loads at offsets at or past the resource's size return zero.
 constexpr int kBufferFlags = 0x00020000;
@@ -332,13 +352,7 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t bx, int64_t
   auto store_rows = [&](auto& tile, int row, int kg, const G (&v)[KV]) {
     if constexpr (SPLIT) {
       bf16x8_t pl[P];
-#pragma unroll
-      for (int e = 0; e < KV; ++e) {
-        __bf16 o[P];
-        split_bf16<P>(v[e], o);
-#pragma unroll
-        for (int p = 0; p < P; ++p) pl[p][e] = o[p];
-      }
+      split_bf16_group<P, KV>(v, pl);
 #pragma unroll
       for (int p = 0; p < P; ++p) *reinterpret_cast<bf16x8_t*>(&tile[p][row][kg * KV]) = pl[p];
     } else {

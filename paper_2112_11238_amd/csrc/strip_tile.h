@@ -96,13 +96,7 @@ __device__ __forceinline__ void strip_run(const ModeArgs& a, int64_t by, int64_t
       if (row >= BN) continue;
       if constexpr (SPLIT) {
         bf16x8_t pl[P];
-#pragma unroll
-        for (int e = 0; e < KV; ++e) {
-          __bf16 o[P];
-          split_bf16<P>(lr[s][e], o);
-#pragma unroll
-          for (int p = 0; p < P; ++p) pl[p][e] = o[p];
-        }
+        split_bf16_group<P, KV>(lr[s], pl);
 #pragma unroll
         for (int p = 0; p < P; ++p) *reinterpret_cast<bf16x8_t*>(&sL[p][row][kg * KV]) = pl[p];
       } else {
@@ -170,13 +164,7 @@ __device__ __forceinline__ void strip_run(const ModeArgs& a, int64_t by, int64_t
       const int row = xrow[s], kg = xkg[s];
       if constexpr (SPLIT) {
         bf16x8_t pl[P];
-#pragma unroll
-        for (int e = 0; e < KV; ++e) {
-          __bf16 o[P];
-          split_bf16<P>(xr[s][e], o);
-#pragma unroll
-          for (int p = 0; p < P; ++p) pl[p][e] = o[p];
-        }
+        split_bf16_group<P, KV>(xr[s], pl);
 #pragma unroll
         for (int p = 0; p < P; ++p)
           *reinterpret_cast<bf16x8_t*>(&sX[buf][p][row][kg * KV]) = pl[p];
