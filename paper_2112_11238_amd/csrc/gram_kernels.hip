@@ -49,21 +49,29 @@ template <typename E>
 constexpr int strip_br() { return sizeof(E) == 8 ? 32 : 64; }
 constexpr int64_t kMaxStripSplits = 2048;
 
-template <typename E, int NB, int MB, bool INNER>
+template <typename E, int NB, int MB, bool INNER, bool VEC = false>
 __global__ __launch_bounds__(kThreads, 2) void gram_strip_kernel(GramArgs g, int64_t chunks,
                                                                  int64_t splits) {
   constexpr int BR = strip_br<E>();
   __shared__ __attribute__((aligned(16))) char lds[strip_lds_bytes<E, NB, MB, BR>()];
   const int64_t s = blockIdx.x;
   const int64_t cb = s * chunks / splits, ce = (s + 1) * chunks / splits;
-  gram_strip<E, NB, MB, BR, INNER>(g, cb, ce, static_cast<E*>(g.part) + s * g.n * g.m, lds);
+  gram_strip<E, NB, MB, BR, INNER, VEC>(g, cb, ce, static_cast<E*>(g.part) + s * g.n * g.m,
+                                        lds);
 }
 
 using StripGramFn = void (*)(GramArgs, int64_t, int64_t);
 
+// vec: inner layout with fiber groups of 16 bytes (I_l a multiple of the
+// group, Q and P 16-byte aligned)
 template <typename E>
-StripGramFn strip_gram_fn(int64_t n, int64_t m, bool inner) {
+StripGramFn strip_gram_fn(int64_t n, int64_t m, bool inner, bool vec) {
   const bool n2 = n <= 32, m2 = m <= 32;
+  if (inner && vec) {
+    if (n2)
+      return m2 ? gram_strip_kernel<E, 2, 2, true, true> : gram_strip_kernel<E, 2, 4, true, true>;
+    return m2 ? gram_strip_kernel<E, 4, 2, true, true> : gram_strip_kernel<E, 4, 4, true, true>;
+  }
   if (inner) {
     if (n2) return m2 ? gram_strip_kernel<E, 2, 2, true> : gram_strip_kernel<E, 2, 4, true>;
     return m2 ? gram_strip_kernel<E, 4, 2, true> : gram_strip_kernel<E, 4, 4, true>;
@@ -145,9 +153,12 @@ hipError_t launch_gram(int dtype, const void* Q, const void* P, int64_t Il, int6
     g.m = m;
     g.Ir = Ir;
     const bool inner = Il > 1;
+    const int64_t kv = 16 / static_cast<int64_t>(es);
+    const bool vec = inner && Il % kv == 0 && reinterpret_cast<uintptr_t>(Q) % 16 == 0 &&
+                     reinterpret_cast<uintptr_t>(P) % 16 == 0;
     const int64_t chunks = strip_chunks(Il, Ir, es);
-    const StripGramFn fn = dtype == KP_F64 ? strip_gram_fn<double>(n, m, inner)
-                                           : strip_gram_fn<float>(n, m, inner);
+    const StripGramFn fn = dtype == KP_F64 ? strip_gram_fn<double>(n, m, inner, vec)
+                                           : strip_gram_fn<float>(n, m, inner, vec);
     int64_t splits = strip_slots(fn);
     if (splits > chunks) splits = chunks;
     if (splits > kMaxStripSplits) splits = kMaxStripSplits;

@@ -31,8 +31,11 @@ constexpr size_t strip_lds_bytes() {
 // wave order, ((w0 + w1) + w2) + w3.
 // INNER (Il > 1): a staging task is one fiber and KV consecutive rows, lanes
 // walk along fibers (contiguous in memory). Lead (Il == 1): a task is one
-// row and KV consecutive fibers, lanes walk along rows.
-template <typename E, int NB, int MB, int BR, bool INNER>
+// row and KV consecutive fibers, lanes walk along rows. INNER with VEC
+// (Il a multiple of KV, Q and P 16-byte aligned): a task is one row and KV
+// consecutive fibers, which are adjacent in memory, so it is one 16-byte
+// load and one 16-byte LDS store; lanes walk along the fiber groups.
+template <typename E, int NB, int MB, int BR, bool INNER, bool VEC = false>
 __device__ __forceinline__ void gram_strip(const GramArgs& g, int64_t c_begin, int64_t c_end,
                                            E* __restrict__ out, char* __restrict__ lds) {
   using GT = GramT<E>;
@@ -74,8 +77,36 @@ __device__ __forceinline__ void gram_strip(const GramArgs& g, int64_t c_begin, i
   const auto prs = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<void*>(g.P), 0, static_cast<int>(g.Il * g.m * g.Ir * sizeof(E)),
       tile::kBufferFlags);
+  constexpr bool GV = INNER && VEC;   // grouped fibers on the inner layout
+  constexpr int FG = BR / KV;          // fiber groups per chunk
+  typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+  auto load_vec = [&](__amdgpu_buffer_rsrc_t rs, uint32_t r, uint32_t i, uint32_t rows,
+                      uint32_t len, E (&dst)[KV]) {
+    const uint32_t b = r / Il;
+    const uint32_t off = (r < F && i < rows) ? ((r - b * Il) + Il * len * b + Il * i) * sizeof(E)
+                                            : kOut;
+    const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, static_cast<int>(off), 0, 0);
+    const frag f = __builtin_bit_cast(frag, v);
+#pragma unroll
+    for (int e = 0; e < KV; ++e) dst[e] = f[e];
+  };
   auto load = [&](int64_t ch) {
     const uint32_t r0 = static_cast<uint32_t>(ch) * BR;
+    if constexpr (GV) {
+#pragma unroll
+      for (int s = 0; s < NQ; ++s) {
+        const int id = t + s * kThreads;
+        const uint32_t row = id / FG, r = r0 + (id % FG) * KV;
+        load_vec(qrs, r, id < TQ ? row : n, n, n, qv[s]);
+      }
+#pragma unroll
+      for (int s = 0; s < NP; ++s) {
+        const int id = t + s * kThreads;
+        const uint32_t row = id / FG, r = r0 + (id % FG) * KV;
+        load_vec(prs, r, id < TP ? row : m, m, m, pv[s]);
+      }
+      return;
+    }
     // INNER: one fiber per task (its base offset computed once, rows at
     // stride Il); lead: one row per task, fibers at stride len
 #pragma unroll
@@ -120,6 +151,27 @@ __device__ __forceinline__ void gram_strip(const GramArgs& g, int64_t c_begin, i
     }
   };
   auto store = [&](int buf) {
+    if constexpr (GV) {
+#pragma unroll
+      for (int s = 0; s < NQ; ++s) {
+        const int id = t + s * kThreads;
+        if (id >= TQ) continue;
+        frag f;
+#pragma unroll
+        for (int e = 0; e < KV; ++e) f[e] = qv[s][e];
+        *reinterpret_cast<frag*>(&sQ[buf][id / FG][(id % FG) * KV]) = f;
+      }
+#pragma unroll
+      for (int s = 0; s < NP; ++s) {
+        const int id = t + s * kThreads;
+        if (id >= TP) continue;
+        frag f;
+#pragma unroll
+        for (int e = 0; e < KV; ++e) f[e] = pv[s][e];
+        *reinterpret_cast<frag*>(&sP[buf][id / FG][(id % FG) * KV]) = f;
+      }
+      return;
+    }
 #pragma unroll
     for (int s = 0; s < NQ; ++s) {
       const int id = t + s * kThreads;

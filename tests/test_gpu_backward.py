@@ -20,6 +20,9 @@ CASES = [
     ((4, 4, 4, 4, 4, 4), (6, 6, 6, 6, 6, 6)),
     # tens of thousands of fibers per factor gradient: several chunks per workgroup
     ((60, 50, 40, 30), (20, 64, 33, 9)),
+    # inner strides that are multiples of 4 (16-byte fiber groups) with a
+    # ragged last chunk
+    ((36, 12, 20), (8, 16, 24)),
 ]
 
 
