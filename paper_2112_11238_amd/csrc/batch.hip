@@ -43,7 +43,8 @@ constexpr int64_t kGramChunks = 8;    // fiber chunks per streaming gram task
 
 // ST_MODE: k-loop tiles; ST_STRIP: strip tasks (a run of fiber tiles of one
 // n block, strip_tile.h); ST_GRAM: 64 x 64 gram tiles of one split;
-// ST_GSTRIP: one streaming gram partial (gram_strip.h); ST_REDUCE: 16
+// ST_GSTRIP: one streaming gram partial (gram_strip.h; variant bit 3: 16-byte
+// fiber groups on the inner layout); ST_REDUCE: 16
 // outputs of the fixed-order sum of a gram's partial tiles.
 enum StageKind { ST_MODE = 0, ST_GRAM = 1, ST_REDUCE = 2, ST_STRIP = 3, ST_GSTRIP = 4 };
 
@@ -204,7 +205,8 @@ __device__ __forceinline__ void run_task(const BStage& S, int64_t tile_id, char*
   } else if constexpr (KIND == ST_GSTRIP) {
     const int64_t cb = tile_id * S.ntiles / S.splits;
     const int64_t ce = (tile_id + 1) * S.ntiles / S.splits;
-    gram::gram_strip<E, (VAR & 4) ? 4 : 2, (VAR & 2) ? 4 : 2, gstrip_br<E>(), INNER>(
+    gram::gram_strip<E, (VAR & 4) ? 4 : 2, (VAR & 2) ? 4 : 2, gstrip_br<E>(), INNER,
+                     INNER && (VAR & 8) != 0>(
         S.g, cb, ce, static_cast<E*>(S.g.part) + tile_id * S.g.n * S.g.m, lds);
   } else {
     gram::gram_reduce_block<E>(static_cast<const E*>(S.g.part), S.splits, S.g.n, S.g.m,
@@ -255,14 +257,14 @@ struct GroupTable {
   static constexpr auto mode = group_fns<FORM, ST_MODE>(std::make_integer_sequence<int, NM>{});
   static constexpr auto strip = group_fns<FORM, ST_STRIP>(std::make_integer_sequence<int, NS>{});
   static constexpr auto gram = group_fns<FORM, ST_GRAM>(std::make_integer_sequence<int, 2>{});
-  static constexpr auto gstrip = group_fns<FORM, ST_GSTRIP>(std::make_integer_sequence<int, 8>{});
+  static constexpr auto gstrip = group_fns<FORM, ST_GSTRIP>(std::make_integer_sequence<int, 16>{});
   static constexpr auto reduce = group_fns<FORM, ST_REDUCE>(std::make_integer_sequence<int, 1>{});
   static GroupFn get(int kind, int var) {
     switch (kind) {
       case ST_MODE: return var >= 0 && var < NM ? mode[var] : nullptr;
       case ST_STRIP: return var >= 0 && var < NS ? strip[var] : nullptr;
       case ST_GRAM: return var >= 0 && var < 2 ? gram[var] : nullptr;
-      case ST_GSTRIP: return var >= 0 && var < 8 ? gstrip[var] : nullptr;
+      case ST_GSTRIP: return var >= 0 && var < 16 ? gstrip[var] : nullptr;
       case ST_REDUCE: return var == 0 ? reduce[0] : nullptr;
       default: return nullptr;
     }
@@ -539,7 +541,12 @@ int build_plan(int count, const kp_batch_item* items, int prec, char* ws_base, P
           if (splits < 1) splits = 1;
           g.part = region(static_cast<size_t>(splits * g.n * g.m) * es);
           b.kind = ST_GSTRIP;
-          b.variant = (inner ? 1 : 0) + (g.m > 32 ? 2 : 0) + (g.n > 32 ? 4 : 0);
+          // + 8: inner fibers staged in 16-byte groups (I_l a multiple of
+          // the group, Q and P 16-byte aligned)
+          const bool gv = inner && Il % static_cast<int64_t>(16 / es) == 0 &&
+                          reinterpret_cast<uintptr_t>(g.Q) % 16 == 0 &&
+                          reinterpret_cast<uintptr_t>(g.P) % 16 == 0;
+          b.variant = (inner ? 1 : 0) + (g.m > 32 ? 2 : 0) + (g.n > 32 ? 4 : 0) + (gv ? 8 : 0);
           b.ntiles = chunks;
           b.splits = splits;
           b.tx = static_cast<int32_t>(splits);
