@@ -157,9 +157,11 @@ int kp_tucker(const kp_tensor* T, const kp_matrix* const* L, kp_tensor* S,
  *   conj != 0: S = T x_1 L_1^* ... x_d L_d^*, ^* the conjugate transpose,
  *              L_mu is m_mu x n_mu.
  * S is (2, n_1, ..., n_d) in the same layout. Modes are applied in order
- * 1..d; each is two real mu-mode products on the real kernels (real and
- * imaginary part of the factor) and one element-wise pass adding i times the
- * second. prec as for kp_mump (the split forms need F32).
+ * 1..d; each is two real mu-mode products on the real kernels, with the real
+ * and then the imaginary part of the factor, the second adding i (or -i for
+ * the conjugate transpose) times its result in its epilogue. prec as for
+ * kp_mump (the split forms need F32).
+ * The factor parts are first packed, as applied, into the workspace.
  * ws_bytes >= kp_tucker_complex_workspace(...). Errors: as kp_tucker, and
  * KP_ERR_ORDER for order < 2, KP_ERR_SHAPE if T's first mode is not 2 or the
  * parts of a factor differ in size, KP_ERR_NULL for Lim[k] without Lre[k]. */

@@ -9,8 +9,10 @@
 // interleaved complex matrix). Mode mu of the complex product is then
 //   Y = X x_(mu+1) Re(L) + i s (X x_(mu+1) Im(L)),
 // two real mu-mode products on the same real kernels (the size-2 mode sits
-// in the fibers' leading index) and one element-wise pass that adds i s B,
-// s = +1 for L and -1 for the conjugate transpose.
+// in the fibers' leading index), s = +1 for L and -1 for the conjugate
+// transpose. The second product's epilogue adds i s times its value: the
+// parts of one complex output are adjacent fibers, held by neighbouring
+// lanes, so each lane combines with its partner's value before the store.
 #include "kp.h"
 
 #include "kp_common.h"
@@ -19,19 +21,19 @@
 namespace kp {
 namespace {
 
-constexpr int kCT = 256;
+constexpr int kPT = 256;
 
-// y += i s b for `count` complex values stored as (re, im) pairs.
+// dst[i * cols + j] = A(i, j) = src[i * rs + j * cs] for an rows x cols
+// matrix: the factor part as applied, packed k-contiguous.
 template <typename E>
-__global__ __launch_bounds__(kCT) void add_i_times_kernel(E* __restrict__ y,
-                                                          const E* __restrict__ b,
-                                                          int64_t count, E s) {
-  for (int64_t e = blockIdx.x * static_cast<int64_t>(kCT) + threadIdx.x; e < count;
-       e += static_cast<int64_t>(gridDim.x) * kCT) {
-    const E br = b[2 * e], bi = b[2 * e + 1];
-    const E yr = y[2 * e], yi = y[2 * e + 1];
-    y[2 * e] = yr - s * bi;
-    y[2 * e + 1] = yi + s * br;
+__global__ __launch_bounds__(kPT) void pack_kernel(const E* __restrict__ src, int64_t rows,
+                                                   int64_t cols, int64_t rs, int64_t cs,
+                                                   E* __restrict__ dst) {
+  const int64_t total = rows * cols;
+  for (int64_t e = blockIdx.x * static_cast<int64_t>(kPT) + threadIdx.x; e < total;
+       e += static_cast<int64_t>(gridDim.x) * kPT) {
+    const int64_t i = e / cols, j = e - (e / cols) * cols;
+    dst[e] = src[i * rs + j * cs];
   }
 }
 
@@ -60,7 +62,6 @@ struct ComplexPlan {
   int steps;
   int mode[KP_MAX_ORDER];                   // complex mode (0-based) of step s
   int64_t big;                              // largest intermediate (real entries)
-  int64_t bigb;                             // largest product output (real entries)
 };
 
 int validate(const kp_tensor* T, const kp_matrix* const* Lre, const kp_matrix* const* Lim,
@@ -75,7 +76,6 @@ int validate(const kp_tensor* T, const kp_matrix* const* Lre, const kp_matrix* c
   p->d = T->d - 1;
   p->steps = 0;
   p->big = 0;
-  p->bigb = 0;
   int64_t cur[KP_MAX_ORDER];
   for (int k = 0; k < T->d; ++k) cur[k] = T->dims[k];
   for (int k = 0; k < p->d; ++k) {
@@ -96,7 +96,6 @@ int validate(const kp_tensor* T, const kp_matrix* const* Lre, const kp_matrix* c
     p->mode[p->steps] = k;
     cur[k + 1] = a.rows;
     const int64_t out = count_of(cur, T->d);
-    if (Lim[k] && out > p->bigb) p->bigb = out;
     ++p->steps;
     if (out > p->big) p->big = out;
   }
@@ -117,9 +116,14 @@ size_t kp_tucker_complex_workspace(const kp_tensor* T, const kp_matrix* const* L
   if (validate(T, Lre, Lim, conj, prec, &p)) return 0;
   const size_t es = elem_size(T->dtype);
   // two ping-pong buffers for the intermediates (only with two or more
-  // steps) and one for the imaginary-part products
-  const size_t inter = p.steps > 1 ? 2 * align_up(static_cast<size_t>(p.big) * es) : 0;
-  return inter + align_up(static_cast<size_t>(p.bigb) * es);
+  // steps), then every factor part packed k-contiguous
+  size_t total = p.steps > 1 ? 2 * align_up(static_cast<size_t>(p.big) * es) : 0;
+  for (int k = 0; k < p.d; ++k) {
+    const int64_t nm = Lre[k] ? Lre[k]->rows * Lre[k]->cols : 0;
+    total += (Lre[k] ? 1 : 0) * align_up(static_cast<size_t>(nm) * es);
+    total += (Lim[k] ? 1 : 0) * align_up(static_cast<size_t>(nm) * es);
+  }
+  return total;
 }
 
 int kp_tucker_complex(const kp_tensor* T, const kp_matrix* const* Lre,
@@ -149,15 +153,56 @@ int kp_tucker_complex(const kp_tensor* T, const kp_matrix* const* Lre,
   if (need > 0 && (!ws || ws_bytes < need)) return KP_ERR_WORKSPACE;
   if (need > 0 && (overlaps(ws, need, S->data, sb) || overlaps(ws, need, T->data, tb)))
     return KP_ERR_ALIAS;
+  for (int k = 0; k < p.d; ++k) {
+    if (Lre[k] && overlaps(ws, need, Lre[k]->data, matrix_span_bytes(*Lre[k])))
+      return KP_ERR_ALIAS;
+    if (Lim[k] && overlaps(ws, need, Lim[k]->data, matrix_span_bytes(*Lim[k])))
+      return KP_ERR_ALIAS;
+  }
   if (numel(*S) == 0) return KP_OK;
   if (p.steps == 0)
     return hip_status(hipMemcpyAsync(S->data, T->data, sb, hipMemcpyDeviceToDevice, stream));
+  if (!ws) return KP_ERR_WORKSPACE;
 
   const int form = form_of(prec, T->dtype);
   char* w = static_cast<char*>(ws);
   const size_t buf = align_up(static_cast<size_t>(p.big) * es);
   char* pp[2] = {w, w + buf};
-  char* bbuf = w + (p.steps > 1 ? 2 * buf : 0);
+  // factor parts as applied (transposed for the conjugate form), packed
+  // k-contiguous so the product kernels stage them with 16-byte loads
+  char* fw = w + (p.steps > 1 ? 2 * buf : 0);
+  kp_matrix pre[KP_MAX_ORDER], pim[KP_MAX_ORDER];
+  auto pack = [&](const kp_matrix& L, kp_matrix* out) -> int {
+    const kp_matrix a = applied(L, conj);
+    *out = a;
+    out->rs = a.cols;
+    out->cs = 1;
+    out->data = fw;
+    const int64_t total = a.rows * a.cols;
+    fw += align_up(static_cast<size_t>(total) * es);
+    if (total == 0) return KP_OK;
+    const int64_t blocks = (total + kPT - 1) / kPT;
+    const unsigned grid = static_cast<unsigned>(blocks < 1024 ? blocks : 1024);
+    if (T->dtype == KP_F64)
+      hipLaunchKernelGGL(pack_kernel<double>, dim3(grid), dim3(kPT), 0, stream,
+                         static_cast<const double*>(a.data), a.rows, a.cols, a.rs, a.cs,
+                         static_cast<double*>(out->data));
+    else
+      hipLaunchKernelGGL(pack_kernel<float>, dim3(grid), dim3(kPT), 0, stream,
+                         static_cast<const float*>(a.data), a.rows, a.cols, a.rs, a.cs,
+                         static_cast<float*>(out->data));
+    return hip_status(hipGetLastError());
+  };
+  for (int k = 0; k < p.d; ++k) {
+    if (Lre[k]) {
+      st = pack(*Lre[k], &pre[k]);
+      if (st) return st;
+    }
+    if (Lim[k]) {
+      st = pack(*Lim[k], &pim[k]);
+      if (st) return st;
+    }
+  }
   const void* src = T->data;
   int cur = -1;
   for (int s = 0; s < p.steps; ++s) {
@@ -169,27 +214,14 @@ int kp_tucker_complex(const kp_tensor* T, const kp_matrix* const* Lre,
       cur = cur == 0 ? 1 : 0;
       dst = pp[cur];
     }
-    const kp_matrix re = applied(*Lre[k], conj);
-    ModeArgs a = mode_args(src, dst, p.dims[s], T->d, k + 1, re, 0);
+    ModeArgs a = mode_args(src, dst, p.dims[s], T->d, k + 1, pre[k], kAccNone);
     st = hip_status(launch_mode(form, a, tile_override(), stream));
     if (st) return st;
     if (Lim[k]) {
-      const kp_matrix im = applied(*Lim[k], conj);
-      ModeArgs b = mode_args(src, bbuf, p.dims[s], T->d, k + 1, im, 0);
+      // dst += i s (src x Im(L)), combined in the product's epilogue
+      ModeArgs b =
+          mode_args(src, dst, p.dims[s], T->d, k + 1, pim[k], conj ? kAccSubI : kAccAddI);
       st = hip_status(launch_mode(form, b, tile_override(), stream));
-      if (st) return st;
-      const int64_t count = count_of(p.dims[s + 1], T->d) / 2;
-      const int64_t blocks = (count + kCT - 1) / kCT;
-      const unsigned grid = static_cast<unsigned>(blocks < 4096 ? blocks : 4096);
-      if (T->dtype == KP_F64)
-        hipLaunchKernelGGL(add_i_times_kernel<double>, dim3(grid), dim3(kCT), 0, stream,
-                           static_cast<double*>(dst), reinterpret_cast<const double*>(bbuf),
-                           count, conj ? -1.0 : 1.0);
-      else
-        hipLaunchKernelGGL(add_i_times_kernel<float>, dim3(grid), dim3(kCT), 0, stream,
-                           static_cast<float*>(dst), reinterpret_cast<const float*>(bbuf),
-                           count, conj ? -1.0f : 1.0f);
-      st = hip_status(hipGetLastError());
       if (st) return st;
     }
     src = dst;

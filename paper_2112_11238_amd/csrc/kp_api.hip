@@ -325,7 +325,8 @@ int kp_mump(const kp_tensor* T, const kp_matrix* L, int mu, kp_tensor* S, int pr
       overlaps(S->data, sb, L->data, matrix_span_bytes(*L)))
     return KP_ERR_ALIAS;
   if (numel(*S) == 0) return KP_OK;
-  const ModeArgs a = mode_args(T->data, S->data, T->dims, T->d, mu - 1, *L, accumulate);
+  const ModeArgs a =
+      mode_args(T->data, S->data, T->dims, T->d, mu - 1, *L, accumulate ? kAccAdd : kAccNone);
   return hip_status(launch_mode(form_of(prec, T->dtype), a, tile_override(), stream));
 }
 

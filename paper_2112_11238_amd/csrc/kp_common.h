@@ -26,8 +26,14 @@ struct ModeArgs {
   const void* L;
   int64_t Il, m, n, Ir;
   int64_t rs, cs;
-  int accumulate;
+  int accumulate;  // an Acc value
 };
+
+// What the epilogue does with a computed value v at its output y:
+// overwrite, add, or add i v / -i v on interleaved complex data, where the
+// real and imaginary parts of one complex entry are adjacent fibers (I_l
+// even, the pair index fastest).
+enum Acc { kAccNone = 0, kAccAdd = 1, kAccAddI = 2, kAccSubI = 3 };
 
 // Tile choice for the mode kernels. nb = 16-wide blocks along n per
 // workgroup, fb = 16-wide fiber blocks per wave (4 waves per workgroup),

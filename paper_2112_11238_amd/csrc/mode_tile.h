@@ -63,6 +63,16 @@ __device__ __forceinline__ void split_bf16_group(const float (&x)[KV], V8 (&pl)[
   }
 }
 
+// Epilogue store of one output value y at byte offset off (past the
+// resource: dropped) by the lane holding fiber column c: overwrite, add, or
+// (inner layout only) add +-i times the value on interleaved complex data.
+// The parts of one complex entry are the adjacent fibers held by lanes c and
+// c ^ 1, so each lane takes its partner's value: re += -s im(v),
+// im += s re(v). acc is uniform across the wave, so every lane shuffles.
+template <bool INNER, typename G>
+__device__ __forceinline__ void store_out(G y, __amdgpu_buffer_rsrc_t rs, uint32_t off, int acc,
+                                          int c);
+
 // Buffer resource word 3 for raw (unformatted, unswizzled) buffers on the
 // gfx9 family; loads at offsets at or past the resource's size return zero.
 constexpr int kBufferFlags = 0x00020000;
@@ -89,6 +99,20 @@ __device__ __forceinline__ void buffer_store(G v, __amdgpu_buffer_rsrc_t rs, uin
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), rs,
                                           static_cast<int>(off), 0, 0);
   }
+}
+
+template <bool INNER, typename G>
+__device__ __forceinline__ void store_out(G y, __amdgpu_buffer_rsrc_t rs, uint32_t off, int acc,
+                                          int c) {
+  if constexpr (INNER) {
+    if (acc >= kAccAddI) {
+      const G other = __shfl_xor(y, 1);
+      const G s = acc == kAccAddI ? G(1) : G(-1);
+      y = (c & 1) ? s * other : -s * other;
+    }
+  }
+  if (acc != kAccNone) y += buffer_load<G>(rs, off);
+  buffer_store<G>(y, rs, off);
 }
 
 // Per-form constants. The LDS tiles hold rows (an n index or a fiber) whose
@@ -516,11 +540,7 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t bx, int64_t
         }
       }
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        G y = val[v];
-        if (a.accumulate) y += buffer_load<G>(yrs, off[v]);
-        buffer_store<G>(y, yrs, off[v]);
-      }
+      for (int v = 0; v < 4; ++v) store_out<INNER, G>(val[v], yrs, off[v], a.accumulate, c);
     }
 }
 

@@ -241,9 +241,7 @@ __device__ __forceinline__ void strip_run(const ModeArgs& a, int64_t by, int64_t
             const uint32_t f = f0 + w * 16 * FB + q * 16 + FT::row(lane, v);
             off = (f < F && i < n) ? (i + n * f) * sizeof(G) : kOut;
           }
-          G y = val[v];
-          if (a.accumulate) y += buffer_load<G>(yrs, off);
-          buffer_store<G>(y, yrs, off);
+          store_out<INNER, G>(val[v], yrs, off, a.accumulate, c);
         }
       }
     if (nx < ntiles) store_x(buf ^ 1);
