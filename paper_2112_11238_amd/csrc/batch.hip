@@ -209,9 +209,9 @@ __device__ __forceinline__ void run_task(const BStage& S, int64_t tile_id, char*
                      INNER && (VAR & 8) != 0>(
         S.g, cb, ce, static_cast<E*>(S.g.part) + tile_id * S.g.n * S.g.m, lds);
   } else {
-    gram::gram_reduce_block<E>(static_cast<const E*>(S.g.part), S.splits, S.g.n, S.g.m,
-                               static_cast<E*>(S.dL), S.rs, S.cs, tile_id,
-                               reinterpret_cast<E*>(lds));
+    gram::gram_reduce_block<E, 16>(static_cast<const E*>(S.g.part), S.splits, S.g.n, S.g.m,
+                                   static_cast<E*>(S.dL), S.rs, S.cs, tile_id,
+                                   reinterpret_cast<E*>(lds));
   }
 }
 

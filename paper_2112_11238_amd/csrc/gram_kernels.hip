@@ -33,12 +33,39 @@ __global__ __launch_bounds__(kThreads, 2) void gram_kernel(GramArgs g) {
 
 // dL(i, j) = sum_s part[s][i][j] in a fixed order, written at dL[i*rs + j*cs];
 // workgroup x handles outputs 16x .. 16x + 15.
-template <typename E>
+template <typename E, int OPB>
 __global__ __launch_bounds__(kThreads) void gram_reduce(const E* __restrict__ part, int64_t splits,
                                                         int64_t n, int64_t m, E* __restrict__ dL,
                                                         int64_t rs, int64_t cs) {
   __shared__ E sred[kThreads];
-  gram_reduce_block<E>(part, splits, n, m, dL, rs, cs, blockIdx.x, sred);
+  gram_reduce_block<E, OPB>(part, splits, n, m, dL, rs, cs, blockIdx.x, sred);
+}
+
+// dL = the fixed-order sum of `splits` partial tiles.
+hipError_t launch_reduce(int dtype, const void* part, int64_t splits, int64_t n, int64_t m,
+                         void* dL, int64_t rs, int64_t cs, hipStream_t stream) {
+  const int opb = reduce_outputs(splits, n * m);
+  const unsigned blocks = static_cast<unsigned>((n * m + opb - 1) / opb);
+  if (dtype == KP_F64) {
+    const double* p = static_cast<const double*>(part);
+    double* o = static_cast<double*>(dL);
+    if (opb == 4)
+      hipLaunchKernelGGL((gram_reduce<double, 4>), dim3(blocks), dim3(kThreads), 0, stream, p,
+                         splits, n, m, o, rs, cs);
+    else
+      hipLaunchKernelGGL((gram_reduce<double, 16>), dim3(blocks), dim3(kThreads), 0, stream, p,
+                         splits, n, m, o, rs, cs);
+  } else {
+    const float* p = static_cast<const float*>(part);
+    float* o = static_cast<float*>(dL);
+    if (opb == 4)
+      hipLaunchKernelGGL((gram_reduce<float, 4>), dim3(blocks), dim3(kThreads), 0, stream, p,
+                         splits, n, m, o, rs, cs);
+    else
+      hipLaunchKernelGGL((gram_reduce<float, 16>), dim3(blocks), dim3(kThreads), 0, stream, p,
+                         splits, n, m, o, rs, cs);
+  }
+  return hipGetLastError();
 }
 
 constexpr int kBR = 32;
@@ -141,8 +168,6 @@ hipError_t launch_gram(int dtype, const void* Q, const void* P, int64_t Il, int6
                        hipStream_t stream) {
   if (n == 0 || m == 0) return hipSuccess;
   const size_t es = dtype == KP_F64 ? 8 : 4;
-  const int64_t total = n * m;
-  const unsigned rblocks = static_cast<unsigned>((total + 15) / 16);
   if (use_strip(Il, n, m, Ir, es)) {
     GramArgs g{};
     g.Q = Q;
@@ -167,15 +192,7 @@ hipError_t launch_gram(int dtype, const void* Q, const void* P, int64_t Il, int6
                        chunks, splits);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (dtype == KP_F64)
-      hipLaunchKernelGGL(gram_reduce<double>, dim3(rblocks), dim3(kThreads), 0, stream,
-                         static_cast<const double*>(part), splits, n, m, static_cast<double*>(dL),
-                         rs, cs);
-    else
-      hipLaunchKernelGGL(gram_reduce<float>, dim3(rblocks), dim3(kThreads), 0, stream,
-                         static_cast<const float*>(part), splits, n, m, static_cast<float*>(dL),
-                         rs, cs);
-    return hipGetLastError();
+    return launch_reduce(dtype, part, splits, n, m, dL, rs, cs, stream);
   }
   GramArgs g;
   g.Q = Q;
@@ -205,15 +222,7 @@ hipError_t launch_gram(int dtype, const void* Q, const void* P, int64_t Il, int6
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if (dtype == KP_F64)
-    hipLaunchKernelGGL(gram_reduce<double>, dim3(rblocks), dim3(kThreads), 0, stream,
-                       static_cast<const double*>(part), splits, n, m, static_cast<double*>(dL),
-                       rs, cs);
-  else
-    hipLaunchKernelGGL(gram_reduce<float>, dim3(rblocks), dim3(kThreads), 0, stream,
-                       static_cast<const float*>(part), splits, n, m, static_cast<float*>(dL), rs,
-                       cs);
-  return hipGetLastError();
+  return launch_reduce(dtype, part, splits, n, m, dL, rs, cs, stream);
 }
 
 }  // namespace kp

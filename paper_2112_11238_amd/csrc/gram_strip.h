@@ -265,29 +265,40 @@ __device__ __forceinline__ void gram_strip(const GramArgs& g, int64_t c_begin, i
   __syncthreads();  // the caller may reuse the LDS
 }
 
-// part holds `splits` partial n x m tiles; dL(i, j) = their sum in split
-// order, written at dL[i*rs + j*cs]. A workgroup handles 16 outputs with 16
-// threads each: thread q adds splits q, q + 16, ... and the 16 partial sums
-// are then added in q order.
-template <typename E>
+// Outputs per 256-thread block of the partial-tile reduction: 4 (64
+// threads per output) when many partial tiles meet few outputs (a narrow
+// reduction would run on few CUs, each thread walking a long sum), else 16.
+__host__ __device__ constexpr int reduce_outputs(int64_t splits, int64_t outputs) {
+  return splits >= 256 && outputs < 4096 ? 4 : 16;
+}
+
+// part holds `splits` partial n x m tiles; dL(i, j) = their sum, written at
+// dL[i*rs + j*cs]. A block handles OPB outputs with G = 256 / OPB threads
+// each: thread q adds splits q, q + G, ... and the G partial sums are then
+// added by a fixed pairwise tree (q + h into q for h = G/2, ..., 1), so the
+// result does not depend on scheduling.
+template <typename E, int OPB>
 __device__ __forceinline__ void gram_reduce_block(const E* __restrict__ part, int64_t splits,
                                                   int64_t n, int64_t m, E* __restrict__ dL,
                                                   int64_t rs, int64_t cs, int64_t blk,
                                                   E* __restrict__ sred) {
+  constexpr int G = kThreads / OPB;
   const int t = threadIdx.x;
-  const int o = t & 15, q = t >> 4;
-  const int64_t idx = blk * 16 + o;
+  const int o = t % OPB, q = t / OPB;
+  const int64_t idx = blk * OPB + o;
   const int64_t nm = n * m;
   E s = E(0);
   if (idx < nm)
-    for (int64_t k = q; k < splits; k += 16) s += part[k * nm + idx];
-  sred[q * 16 + o] = s;
+    for (int64_t k = q; k < splits; k += G) s += part[k * nm + idx];
+  sred[t] = s;
   __syncthreads();
+  for (int h = G / 2; h >= 1; h /= 2) {
+    if (q < h) sred[t] += sred[t + h * OPB];
+    __syncthreads();
+  }
   if (q == 0 && idx < nm) {
-    E tot = sred[o];
-    for (int k = 1; k < 16; ++k) tot += sred[k * 16 + o];
     const int64_t i = idx / m, j = idx - (idx / m) * m;
-    dL[i * rs + j * cs] = tot;
+    dL[i * rs + j * cs] = sred[o];
   }
   __syncthreads();
 }
