@@ -102,3 +102,21 @@ def test_identity_and_real_factors(kp, form):
     got = S.to(torch.complex128).cpu().numpy()
     assert np.all(np.abs(got.real - ref.real) <= b) and np.all(np.abs(got.imag - ref.imag) <= b)
     assert torch.equal(same, dev(T, CDT[form]))
+
+
+def test_order_one_and_transposed_views(kp):
+    rng = np.random.default_rng(11)
+    v = rng.standard_normal(40) + 1j * rng.standard_normal(40)
+    A = rng.standard_normal((40, 25)) + 1j * rng.standard_normal((40, 25))
+    # conjugate transpose of a 40 x 25 factor maps length 40 to length 25
+    S = kp.tucker_complex(dev(v, torch.complex128), [dev(A, torch.complex128)], conj=True)
+    torch.cuda.synchronize()
+    ref = A.conj().T @ v
+    assert np.max(np.abs(S.cpu().numpy() - ref)) <= 1e-13 * np.max(np.abs(ref))
+    # a transposed (non-contiguous) complex factor view
+    T = rng.standard_normal((5, 6, 7)) + 1j * rng.standard_normal((5, 6, 7))
+    B = rng.standard_normal((6, 4)) + 1j * rng.standard_normal((6, 4))       # B^T is 4 x 6
+    S = kp.tucker_complex(dev(T, torch.complex128), [None, dev(B, torch.complex128).t(), None])
+    torch.cuda.synchronize()
+    ref = oracle.ztucker(T, [None, B.T, None])
+    assert np.max(np.abs(S.cpu().numpy() - ref)) <= 1e-13 * np.max(np.abs(ref))

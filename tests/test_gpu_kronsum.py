@@ -59,3 +59,19 @@ def test_kronsum_heat_laplacian(kp):
     # eigenvector of each tridiagonal factor: eigenvalue -4/h^2 sin^2(pi h / 2)
     lam = -4.0 / h ** 2 * np.sin(np.pi * h / 2) ** 2
     assert np.max(np.abs(S.cpu().numpy() - 3 * lam * V)) <= 1e-9 * np.max(np.abs(3 * lam * V))
+
+
+def test_kronsum_order_one_and_strided_factors(kp):
+    rng = np.random.default_rng(71)
+    v = rng.standard_normal(37)
+    A = rng.standard_normal((37, 37))
+    S = kp.kronsum(to_dev(v, torch.float64), [to_dev(A, torch.float64)])
+    torch.cuda.synchronize()
+    assert np.max(np.abs(S.cpu().numpy() - A @ v)) <= 1e-13 * np.max(np.abs(A @ v))
+    # transposed views (non-unit column stride) give the transposed sum
+    T = rng.standard_normal((6, 9, 5))
+    As = [rng.standard_normal((k, k)) for k in (6, 9, 5)]
+    S = kp.kronsum(to_dev(T, torch.float64), [to_dev(B, torch.float64).t() for B in As])
+    torch.cuda.synchronize()
+    ref = oracle.kronsumv(T, [B.T for B in As])
+    assert np.max(np.abs(S.cpu().numpy() - ref)) <= 1e-13 * np.max(np.abs(ref))

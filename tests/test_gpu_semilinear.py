@@ -121,3 +121,20 @@ def test_imex_experiment_reproduces_printed_results(kp):
     assert round(np.mean(its)) == 2, np.mean(its)
     assert sum(a != b for a, b in zip(its, rits)) <= 2, (its, rits)
     assert _rel(u, ref) <= 1e-7
+
+
+def test_pcg_identity_preconditioner_factors(kp):
+    """None entries of the preconditioner list are identity factors."""
+    ns = (6, 7, 8)
+    Ms = kp_workloads.spd_matrices(31, ns)
+    Ps = kp_workloads.spd_matrices(32, ns, shift=0.5)
+    Ps[1] = None
+    B = np.random.default_rng(33).standard_normal(ns)
+    X, it, res = kp.pcg_kronsum(to_dev(B, torch.float64), [to_dev(M, torch.float64) for M in Ms],
+                                [None if P is None else to_dev(P, torch.float64) for P in Ps],
+                                tol=1e-11, maxit=300)
+    torch.cuda.synchronize()
+    rx, rit, _ = oracle.pcg(lambda v: oracle.kronsumv(v, Ms), B, np.zeros(ns),
+                            lambda r: oracle.tucker(r, Ps), 1e-11, 300)
+    assert res <= 1e-11 and abs(it - rit) <= 1
+    assert _rel(X.cpu().numpy(), rx) <= 1e-8
