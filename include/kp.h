@@ -10,8 +10,15 @@
  *   - its gradient (not in the paper; derived from the Lemma relating the
  *     Tucker operator to L_d (x) ... (x) L_1 and the Kronecker transpose rule,
  *     Appendix A property 5);
+ *   - the action of a Kronecker sum (Sec. 2);
+ *   - the complex Tucker operator and its conjugate-transpose form (Sec. 2
+ *     over C; Sec. 3, spectral transforms);
  *   - the exponential of a small matrix, the 1-D factor of the exponential of
- *     a Kronecker sum (Sec. 3.3).
+ *     a Kronecker sum (Sec. 3.3);
+ *   - tridiagonal inverses, preconditioned conjugate gradients on a
+ *     Kronecker-sum system with a Kronecker-product (ADI-type) preconditioner
+ *     and the backward-forward Euler steps of the semilinear experiment
+ *     (Sec. 3.4, Sec. 4.5).
  *
  * Memory layout
  *   A tensor is column-major: mode 1 is contiguous, exactly the linear order
@@ -26,9 +33,11 @@
  *
  * Ownership and synchronisation
  *   The caller owns every buffer (device memory for tensors, factors, outputs
- *   and workspaces). The library never allocates device memory, never frees
- *   caller memory and never synchronises: every call only enqueues kernels on
- *   `stream` and returns. Calls may be captured into a HIP graph.
+ *   and workspaces). The library never allocates device memory and never
+ *   frees caller memory. Every call except the two iterative solvers
+ *   (kp_pcg_kronsum, kp_semilinear_imex_f64, which wait for `stream` once
+ *   per iteration) only enqueues kernels on `stream` and returns; those
+ *   calls may be captured into a HIP graph.
  *   Outputs must not overlap inputs (KP_ERR_ALIAS).
  *
  * Errors
