@@ -109,11 +109,11 @@ const Variant* find_variant(int form, const ModeTile& t) {
   return nullptr;
 }
 
-// Default tiles, chosen from tile sweeps on cube200 (m = n = 200), heat128
-// (n = 128), the d = 3 n = 324 cube and small modes: FP64 favours 7 (or, at
-// n = 128, 4) blocks along n with 8-wide k chunks (small LDS and register
-// footprint: 4 waves/SIMD), with two chunks of loads in flight once m >= 256;
-// FP32 7 blocks (8 at n <= 128) with two chunks of loads in flight; the
+// Default tiles, chosen from tile sweeps on cubes with n = 128..324 (cube200
+// among them) and small modes: FP64 favours 7 (or, at 112 < n <= 184, 4)
+// blocks along n with 8-wide k chunks (small LDS and register footprint),
+// with two chunks of loads in flight once m >= 256; FP32 7 blocks (8 at
+// n <= 128, 4 at 128 < n <= 184) with two chunks of loads in flight; the
 // BF16 split forms 4 blocks (BF16x6 with two chunks in flight). Short
 // contractions (m <= 64; FP64: m <= 32, or m <= 64 on the lead layout)
 // take strip tiles.
@@ -130,7 +130,7 @@ ModeTile pick_tile(int form, int64_t Il, int64_t m, int64_t n) {
       t.bk = 8;
       t.occ = 3;
       t.fb = 1;
-      t.nb = (n <= 64 || (n > 112 && n <= 128)) ? 4 : 7;
+      t.nb = (n <= 64 || (n > 112 && n <= 184)) ? 4 : 7;
       // long contractions keep two chunks of loads in flight
       if (t.nb == 7 && m >= 256) {
         t.occ = 2;
@@ -142,7 +142,7 @@ ModeTile pick_tile(int form, int64_t Il, int64_t m, int64_t n) {
     if (n <= 16) { t.nb = 1; t.fb = 4; }
     else if (n <= 32) { t.nb = 2; t.fb = 2; }
     else if (n <= 64) { t.nb = 4; t.fb = 1; }
-    else { t.nb = n <= 128 ? 8 : 7; t.fb = 1; t.pf = 2; }
+    else { t.nb = n <= 128 ? 8 : (n <= 184 ? 4 : 7); t.fb = 1; t.pf = 2; }
   } else {
     t.bk = 32;
     if (n <= 16) { t.nb = 1; t.fb = 4; }
