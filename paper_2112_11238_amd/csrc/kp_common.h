@@ -56,7 +56,7 @@ bool mode_tile_supported(int form, const ModeArgs& a, const ModeTile& t);
 // *out with its occ and pf filled in; false if none.
 bool resolve_mode_tile(int form, const ModeTile& t, ModeTile* out);
 // Built-in default tile by form and the mode's sizes.
-ModeTile builtin_mode_tile(int form, int64_t Il, int64_t m, int64_t n);
+ModeTile builtin_mode_tile(int form, int64_t Il, int64_t m, int64_t n, int64_t Ir);
 // Tile-table lookup (kp_tune.hip); false if the key has no entry.
 bool tuned_tile(int form, int64_t Il, int64_t m, int64_t n, int64_t Ir, ModeTile* out);
 // Compiled tiles as (nb, fb, bk, occ, pf, kind) sextuples; returns the count.
@@ -65,7 +65,7 @@ int list_batch_variants(int form, int32_t* out, int cap);
 // Strip tiles (strip_kernels.hip): default choice for m <= the form's
 // largest strip (false otherwise), resolution against the compiled list,
 // listing, and the launch of one piece (< 2^31 bytes) of a product.
-bool strip_default(int form, int64_t Il, int64_t m, int64_t n, ModeTile* out);
+bool strip_default(int form, int64_t Il, int64_t m, int64_t n, int64_t Ir, ModeTile* out);
 bool strip_resolve(int form, const ModeTile& t, ModeTile* out);
 int list_strip_variants(int form, int32_t* out, int cap);
 hipError_t launch_strip(int form, const ModeArgs& a, const ModeTile& t, hipStream_t stream);

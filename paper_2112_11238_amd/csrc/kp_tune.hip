@@ -116,7 +116,7 @@ extern "C" int kp_tune_lookup(int form, int64_t Il, int64_t m, int64_t n, int64_
   if (!kp::valid_key(form, Il, m, n, Ir)) return KP_ERR_VALUE;
   kp::ModeTile t;
   const bool tuned = kp::tuned_tile(form, Il, m, n, Ir, &t);
-  if (!tuned) t = kp::builtin_mode_tile(form, Il, m, n);
+  if (!tuned) t = kp::builtin_mode_tile(form, Il, m, n, Ir);
   kp::ModeTile r;
   if (!kp::resolve_mode_tile(form, t, &r)) r = t;
   kp::fill(out, kp::Key{form, Il, m, n, Ir}, r);

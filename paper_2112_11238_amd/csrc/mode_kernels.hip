@@ -117,9 +117,9 @@ const Variant* find_variant(int form, const ModeTile& t) {
 // BF16 split forms 4 blocks (BF16x6 with two chunks in flight). Short
 // contractions (m <= 64; FP64: m <= 32, or m <= 64 on the lead layout)
 // take strip tiles.
-ModeTile pick_tile(int form, int64_t Il, int64_t m, int64_t n) {
+ModeTile pick_tile(int form, int64_t Il, int64_t m, int64_t n, int64_t Ir) {
   ModeTile t{};
-  if (strip_default(form, Il, m, n, &t)) return t;
+  if (strip_default(form, Il, m, n, Ir, &t)) return t;
   t.occ = 0;
   t.pf = 0;
   if (form == FORM_F64) {
@@ -149,19 +149,35 @@ ModeTile pick_tile(int form, int64_t Il, int64_t m, int64_t n) {
     else if (n <= 32) { t.nb = 2; t.fb = 2; }
     else { t.nb = 4; t.fb = 1; t.pf = form == FORM_BF16X6 ? 2 : 0; }
   }
+  // Small problems (64 < n <= 184): when the tile above gives too few
+  // workgroups to fill the chip, the smaller tiles the sweeps favoured there
+  const int64_t F = Il > 1 ? Il * Ir : Ir;
+  const int64_t tiles = ((F + 64 * t.fb - 1) / (64 * t.fb)) * ((n + 16 * t.nb - 1) / (16 * t.nb));
+  const bool split = form == FORM_BF16X3 || form == FORM_BF16X6;
+  if (n > 64 && n <= 184 && tiles < (split ? 512 : 1024)) {
+    t.occ = 0;
+    t.pf = 0;
+    if (split) {
+      if (n <= 112) { t.nb = 2; t.fb = 1; t.bk = 32; }
+    } else if (n <= 112) {
+      t.nb = 2; t.fb = 2; t.bk = 16;
+    } else {
+      t.nb = 4; t.fb = 1; t.bk = 16; t.pf = 2;
+    }
+  }
   return t;
 }
 
 }  // namespace
 
-ModeTile builtin_mode_tile(int form, int64_t Il, int64_t m, int64_t n) {
-  return pick_tile(form, Il, m, n);
+ModeTile builtin_mode_tile(int form, int64_t Il, int64_t m, int64_t n, int64_t Ir) {
+  return pick_tile(form, Il, m, n, Ir);
 }
 
 ModeTile default_mode_tile(int form, const ModeArgs& a) {
   ModeTile t;
   if (tuned_tile(form, a.Il, a.m, a.n, a.Ir, &t)) return t;
-  return pick_tile(form, a.Il, a.m, a.n);
+  return pick_tile(form, a.Il, a.m, a.n, a.Ir);
 }
 
 bool resolve_mode_tile(int form, const ModeTile& t, ModeTile* out) {

@@ -84,19 +84,27 @@ int device_cus() {
 
 }  // namespace
 
-bool strip_default(int form, int64_t Il, int64_t m, int64_t n, ModeTile* out) {
+bool strip_default(int form, int64_t Il, int64_t m, int64_t n, int64_t Ir, ModeTile* out) {
   if (m < 1 || m > max_strip(form)) return false;
+  const int64_t F = Il > 1 ? Il * Ir : Ir;
   // FP64 with 32 < m <= 64: the 48- and 64-long strips (one or two
-  // workgroups per CU) beat the k-loop tile on the lead layout only
-  if (form == FORM_F64 && m > 32 && Il > 1) return false;
+  // workgroups per CU) beat the k-loop tile on the lead layout, and on the
+  // inner layout only for small problems
+  if (form == FORM_F64 && m > 32 && Il > 1 && F > 65536) return false;
   // FP32 with m <= 16: the k-loop tile (one chunk, 16-byte loads) measured
   // faster than the strip
   if (form == FORM_F32 && m <= 16) return false;
   const int kp = form == FORM_BF16X3 || form == FORM_BF16X6
                      ? (m <= 32 ? 32 : 64)
                      : (m <= 16 ? 16 : (m <= 32 ? 32 : (form == FORM_F64 && m <= 48 ? 48 : 64)));
-  const int nb = n <= 16 ? 1 : (n <= 32 ? 2 : 4);
+  int nb = n <= 16 ? 1 : (n <= 32 ? 2 : 4);
+  // small problems: fewer rows per workgroup, so that the workgroups (fiber
+  // tiles times n blocks) still spread over the chip
   ModeTile t{nb, 0, kp, 0, 0, 1};
+  ModeTile r;
+  while (strip_resolve(form, t, &r) && t.nb > 1 &&
+         ((F + 64 * r.fb - 1) / (64 * r.fb)) * ((n + 16 * t.nb - 1) / (16 * t.nb)) < 512)
+    t.nb /= 2;
   return strip_resolve(form, t, out);
 }
 

@@ -72,9 +72,12 @@ def test_set_lookup_list_clear(lib, L, tune):
     assert lib.kp_tune_set(ctypes.byref(entry(L, 1, 1, 40, 8, 8, (2, 2, 32, 0, 0, 1)))) == -9
     assert lib.kp_tune_set(ctypes.byref(entry(L, 1, 1, 8, 8, 8, (2, 2, 32, 0, 0, 2)))) == -9
     assert lib.kp_tune_count() == 0
-    # short contractions default to a strip tile covering m
-    tuned, tile = tune.lookup("f32", 7, 24, 40, 9)
+    # short contractions default to a strip tile covering m; on small
+    # problems with fewer rows per workgroup, so the workgroups fill the chip
+    tuned, tile = tune.lookup("f32", 7, 24, 40, 90000)
     assert not tuned and tile[5] == 1 and tile[2] >= 24 and 16 * tile[0] >= 32
+    tuned, tile = tune.lookup("f32", 7, 24, 40, 9)
+    assert not tuned and tile[5] == 1 and tile[2] >= 24 and tile[0] == 1
     tune.set_tile("f32", 7, 24, 40, 9, (1, 2, 32, 0, 0, 1))
     assert tune.lookup("f32", 7, 24, 40, 9) == (True, (1, 2, 32, 0, 0, 1))
     tune.clear()
@@ -84,9 +87,13 @@ def test_set_lookup_list_clear(lib, L, tune):
     # long FP64 contractions keep two chunks of loads in flight
     assert tune.lookup("f64", 1, 324, 324, 324 * 324) == (False, (7, 1, 8, 2, 2, 0))
     # FP64 with 32 < m <= 64: a strip on the lead layout, the k-loop tile inside
-    assert tune.lookup("f64", 1, 45, 35, 1000) == (False, (4, 1, 48, 0, 0, 1))
-    assert tune.lookup("f64", 1, 60, 64, 1000) == (False, (4, 1, 64, 0, 0, 1))
-    assert tune.lookup("f64", 35, 45, 35, 1000)[1][5] == 0
+    assert tune.lookup("f64", 1, 45, 35, 10 ** 6) == (False, (4, 1, 48, 0, 0, 1))
+    assert tune.lookup("f64", 1, 60, 64, 10 ** 6) == (False, (4, 1, 64, 0, 0, 1))
+    assert tune.lookup("f64", 35, 45, 35, 10000)[1][5] == 0
+    assert tune.lookup("f64", 35, 45, 35, 1000)[1][5] == 1          # small: a strip
+    # small k-loop problems (64 < n <= 184) take smaller tiles
+    assert tune.lookup("f64", 1, 128, 128, 128 * 128)[1][:3] == (4, 1, 16)
+    assert tune.lookup("f64", 1, 200, 200, 200 * 200)[1][:3] == (7, 1, 8)
     tune.set_tile("f64", 40, 200, 200, 200, (4, 1, 16))
     tuned, tile = tune.lookup("f64", 40, 200, 200, 200)
     assert tuned and tile[:3] == (4, 1, 16) and tile[3] > 0 and tile[4:] == (1, 0)  # resolved
