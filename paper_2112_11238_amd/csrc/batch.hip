@@ -308,7 +308,7 @@ struct Plan {
 // Batch variant for a mode product: the tuned / default tile if the executor
 // has it, else the executor's variant with the closest n coverage.
 int pick_batch_variant(int form, const ModeArgs& a) {
-  const ModeTile want = default_mode_tile(form, a);
+  const ModeTile want = default_mode_tile(form, a, false);
   int nv;
   const BVar* vs = host_vars(form, &nv);
   int best = 0;
@@ -355,7 +355,7 @@ int pick_strip_variant(int form, const ModeArgs& a, const ModeTile& want) {
 
 // Kind, variant and task grid of a mode-product stage (b.m set).
 void set_mode_stage(int form, BStage& b) {
-  const ModeTile want = default_mode_tile(form, b.m);
+  const ModeTile want = default_mode_tile(form, b.m, false);
   const bool inner = b.m.Il > 1;
   const int64_t F = inner ? b.m.Il * b.m.Ir : b.m.Ir;
   if (want.kind == 1) {

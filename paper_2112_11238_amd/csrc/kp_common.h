@@ -49,13 +49,17 @@ struct ModeTile {
 hipError_t launch_mode(int form, const ModeArgs& a, const ModeTile* force,
                        hipStream_t stream);
 // Default tile for a problem (what launch_mode uses when force == nullptr).
-ModeTile default_mode_tile(int form, const ModeArgs& a);
+// alone: a standalone launch (small problems then take tiles that spread
+// over the chip); false inside the batched executor, whose launches are
+// filled by many problems at once.
+ModeTile default_mode_tile(int form, const ModeArgs& a, bool alone = true);
 // Whether a tile is one of the compiled variants for this form/layout.
 bool mode_tile_supported(int form, const ModeArgs& a, const ModeTile& t);
 // The compiled variant matching t (occ 0 / pf 0: first match), written to
 // *out with its occ and pf filled in; false if none.
 bool resolve_mode_tile(int form, const ModeTile& t, ModeTile* out);
 // Built-in default tile by form and the mode's sizes.
+// Ir < 0: no adjustment for the problem size.
 ModeTile builtin_mode_tile(int form, int64_t Il, int64_t m, int64_t n, int64_t Ir);
 // Tile-table lookup (kp_tune.hip); false if the key has no entry.
 bool tuned_tile(int form, int64_t Il, int64_t m, int64_t n, int64_t Ir, ModeTile* out);

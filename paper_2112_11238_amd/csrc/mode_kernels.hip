@@ -151,6 +151,8 @@ ModeTile pick_tile(int form, int64_t Il, int64_t m, int64_t n, int64_t Ir) {
   }
   // Small problems (64 < n <= 184): when the tile above gives too few
   // workgroups to fill the chip, the smaller tiles the sweeps favoured there
+  // (Ir < 0: no size adjustment)
+  if (Ir < 0) return t;
   const int64_t F = Il > 1 ? Il * Ir : Ir;
   const int64_t tiles = ((F + 64 * t.fb - 1) / (64 * t.fb)) * ((n + 16 * t.nb - 1) / (16 * t.nb));
   const bool split = form == FORM_BF16X3 || form == FORM_BF16X6;
@@ -174,10 +176,10 @@ ModeTile builtin_mode_tile(int form, int64_t Il, int64_t m, int64_t n, int64_t I
   return pick_tile(form, Il, m, n, Ir);
 }
 
-ModeTile default_mode_tile(int form, const ModeArgs& a) {
+ModeTile default_mode_tile(int form, const ModeArgs& a, bool alone) {
   ModeTile t;
   if (tuned_tile(form, a.Il, a.m, a.n, a.Ir, &t)) return t;
-  return pick_tile(form, a.Il, a.m, a.n, a.Ir);
+  return pick_tile(form, a.Il, a.m, a.n, alone ? a.Ir : -1);
 }
 
 bool resolve_mode_tile(int form, const ModeTile& t, ModeTile* out) {

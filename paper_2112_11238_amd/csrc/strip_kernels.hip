@@ -86,11 +86,13 @@ int device_cus() {
 
 bool strip_default(int form, int64_t Il, int64_t m, int64_t n, int64_t Ir, ModeTile* out) {
   if (m < 1 || m > max_strip(form)) return false;
+  // Ir < 0: no adjustment for the problem size (the batched executor)
+  const bool sized = Ir >= 0;
   const int64_t F = Il > 1 ? Il * Ir : Ir;
   // FP64 with 32 < m <= 64: the 48- and 64-long strips (one or two
   // workgroups per CU) beat the k-loop tile on the lead layout, and on the
   // inner layout only for small problems
-  if (form == FORM_F64 && m > 32 && Il > 1 && F > 65536) return false;
+  if (form == FORM_F64 && m > 32 && Il > 1 && (!sized || F > 65536)) return false;
   // FP32 with m <= 16: the k-loop tile (one chunk, 16-byte loads) measured
   // faster than the strip
   if (form == FORM_F32 && m <= 16) return false;
@@ -102,7 +104,7 @@ bool strip_default(int form, int64_t Il, int64_t m, int64_t n, int64_t Ir, ModeT
   // tiles times n blocks) still spread over the chip
   ModeTile t{nb, 0, kp, 0, 0, 1};
   ModeTile r;
-  while (strip_resolve(form, t, &r) && t.nb > 1 &&
+  while (sized && strip_resolve(form, t, &r) && t.nb > 1 &&
          ((F + 64 * r.fb - 1) / (64 * r.fb)) * ((n + 16 * t.nb - 1) / (16 * t.nb)) < 512)
     t.nb /= 2;
   return strip_resolve(form, t, out);
