@@ -32,16 +32,21 @@ struct PadeCoef {
 };
 
 // C = A * B for n x n column-major matrices in global memory, computed by the
-// whole workgroup through LDS tiles; each thread owns a 2 x 2 piece of a
-// 64 x 64 tile of C.
+// whole workgroup through LDS tiles on the FP64 matrix cores: each of the 16
+// waves owns one 16 x 16 block of a 64 x 64 tile of C and adds four
+// 16x16x4 MFMA products per 16-wide k chunk (operand fragments: lane l holds
+// A(row l mod 16, k l / 16) and B(k l / 16, column l mod 16); result item v
+// of lane l is C(4v + l / 16, l mod 16)).
 __device__ void block_gemm(const double* __restrict__ A, const double* __restrict__ B,
                            double* __restrict__ C, int n, double (*As)[kKc + 1],
                            double (*Bs)[kTile + 1]) {
   const int t = threadIdx.x;
-  const int tx = t % 32, ty = t / 32;  // rows 2tx, 2tx+1; cols 2ty, 2ty+1
+  const int lane = t & 63, w = t >> 6;
+  const int wr = w & 3, wc = w >> 2;  // this wave's 16 x 16 block of the tile
+  const int c = lane & 15, g = lane >> 4;
   for (int i0 = 0; i0 < n; i0 += kTile)
     for (int j0 = 0; j0 < n; j0 += kTile) {
-      double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+      d4_t acc = {0.0, 0.0, 0.0, 0.0};
       for (int k0 = 0; k0 < n; k0 += kKc) {
         // stage A[i0:i0+64, k0:k0+16] and B[k0:k0+16, j0:j0+64]
         for (int e = t; e < kTile * kKc; e += kT) {
@@ -50,29 +55,22 @@ __device__ void block_gemm(const double* __restrict__ A, const double* __restric
           As[r][kk] = (i < n && k < n) ? A[i + static_cast<int64_t>(n) * k] : 0.0;
         }
         for (int e = t; e < kTile * kKc; e += kT) {
-          const int kk = e % kKc, c = e / kKc;
-          const int k = k0 + kk, j = j0 + c;
-          Bs[kk][c] = (k < n && j < n) ? B[k + static_cast<int64_t>(n) * j] : 0.0;
+          const int kk = e % kKc, cc = e / kKc;
+          const int k = k0 + kk, j = j0 + cc;
+          Bs[kk][cc] = (k < n && j < n) ? B[k + static_cast<int64_t>(n) * j] : 0.0;
         }
         __syncthreads();
 #pragma unroll
-        for (int kk = 0; kk < kKc; ++kk) {
-          const double a0 = As[2 * tx][kk], a1 = As[2 * tx + 1][kk];
-          const double b0 = Bs[kk][2 * ty], b1 = Bs[kk][2 * ty + 1];
-          acc[0][0] = fma(a0, b0, acc[0][0]);
-          acc[0][1] = fma(a0, b1, acc[0][1]);
-          acc[1][0] = fma(a1, b0, acc[1][0]);
-          acc[1][1] = fma(a1, b1, acc[1][1]);
-        }
+        for (int kk = 0; kk < kKc; kk += 4)
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(As[16 * wr + c][kk + g],
+                                                    Bs[kk + g][16 * wc + c], acc, 0, 0, 0);
         __syncthreads();
       }
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-          const int i = i0 + 2 * tx + a, j = j0 + 2 * ty + b;
-          if (i < n && j < n) C[i + static_cast<int64_t>(n) * j] = acc[a][b];
-        }
+      for (int v = 0; v < 4; ++v) {
+        const int i = i0 + 16 * wr + 4 * v + g, j = j0 + 16 * wc + c;
+        if (i < n && j < n) C[i + static_cast<int64_t>(n) * j] = acc[v];
+      }
     }
   __syncthreads();
 }
@@ -91,24 +89,36 @@ __device__ double block_max(double v, double* red) {
 }
 
 // Index of the entry of largest magnitude among v over the block (ties: the
-// smallest index), for partial pivoting.
+// smallest index), for partial pivoting: a butterfly within each wave, then
+// one over the 16 wave results. The order (value descending, index
+// ascending) is total, so every lane of a butterfly ends with the same pair.
+__device__ __forceinline__ void argmax_step(double& v, int& idx, int off) {
+  const double o = __shfl_xor(v, off);
+  const int oi = __shfl_xor(idx, off);
+  if (o > v || (o == v && oi < idx)) {
+    v = o;
+    idx = oi;
+  }
+}
+
 __device__ int block_argmax(double v, int idx, double* red, int* redi) {
   const int t = threadIdx.x;
-  red[t] = v;
-  redi[t] = idx;
-  __syncthreads();
-  for (int s = kT / 2; s > 0; s >>= 1) {
-    if (t < s) {
-      const double o = red[t + s];
-      const int oi = redi[t + s];
-      if (o > red[t] || (o == red[t] && oi < redi[t])) {
-        red[t] = o;
-        redi[t] = oi;
-      }
-    }
-    __syncthreads();
+  const int lane = t & 63, w = t >> 6;
+  for (int off = 32; off >= 1; off >>= 1) argmax_step(v, idx, off);
+  if (lane == 0) {
+    red[w] = v;
+    redi[w] = idx;
   }
-  const int r = redi[0];
+  __syncthreads();
+  if (w == 0) {
+    constexpr int kWaves = kT / 64;
+    v = lane < kWaves ? red[lane] : -1.0;
+    idx = lane < kWaves ? redi[lane] : 0x7fffffff;
+    for (int off = kWaves / 2; off >= 1; off >>= 1) argmax_step(v, idx, off);
+    if (lane == 0) redi[kWaves] = idx;
+  }
+  __syncthreads();
+  const int r = redi[kT / 64];
   __syncthreads();
   return r;
 }
