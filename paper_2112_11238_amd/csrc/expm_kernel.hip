@@ -24,8 +24,9 @@ namespace {
 
 constexpr int kT = 1024;       // threads per workgroup
 constexpr int kTile = 64;      // C tile edge of the block GEMM
-constexpr int kKc = 16;        // k chunk of the block GEMM
+constexpr int kKc = 64;        // k chunk of the block GEMM
 constexpr double kTheta13 = 5.371920351148152;
+constexpr int kSmallN = 128;   // largest n whose LU factors stay in LDS
 
 struct PadeCoef {
   double c[14];
@@ -33,10 +34,11 @@ struct PadeCoef {
 
 // C = A * B for n x n column-major matrices in global memory, computed by the
 // whole workgroup through LDS tiles on the FP64 matrix cores: each of the 16
-// waves owns one 16 x 16 block of a 64 x 64 tile of C and adds four
-// 16x16x4 MFMA products per 16-wide k chunk (operand fragments: lane l holds
-// A(row l mod 16, k l / 16) and B(k l / 16, column l mod 16); result item v
-// of lane l is C(4v + l / 16, l mod 16)).
+// waves owns one 16 x 16 block of a 64 x 64 tile of C and adds one 16x16x4
+// MFMA product per 4 k values of each 64-wide k chunk staged in LDS
+// (operand fragments: lane l holds A(row l mod 16, k l / 16) and
+// B(k l / 16, column l mod 16); result item v of lane l is
+// C(4v + l / 16, l mod 16)).
 __device__ void block_gemm(const double* __restrict__ A, const double* __restrict__ B,
                            double* __restrict__ C, int n, double (*As)[kKc + 1],
                            double (*Bs)[kTile + 1]) {
@@ -126,10 +128,14 @@ __device__ int block_argmax(double v, int idx, double* red, int* redi) {
 __global__ __launch_bounds__(kT) void expm_pade13(const double* __restrict__ Ain, int n,
                                                   double tau, double* __restrict__ Eout,
                                                   double* __restrict__ ws, PadeCoef pc) {
-  __shared__ double As[kTile][kKc + 1];
-  __shared__ double Bs[kKc][kTile + 1];
+  // LDS: the GEMM tiles, or (n <= kSmallN) the LU factors of the Pade
+  // denominator during the solve
+  __shared__ __attribute__((aligned(16))) double smem[kSmallN * kSmallN];
   __shared__ double red[kT];
   __shared__ int redi[kT];
+  __shared__ int spiv[kSmallN], sperm[kSmallN];
+  auto As = reinterpret_cast<double(*)[kKc + 1]>(smem);
+  auto Bs = reinterpret_cast<double(*)[kTile + 1]>(smem + kTile * (kKc + 1));
   const int64_t nn = static_cast<int64_t>(n) * n;
   const double* A = Ain + blockIdx.x * nn;
   double* E = Eout + blockIdx.x * nn;
@@ -190,58 +196,128 @@ __global__ __launch_bounds__(kT) void expm_pade13(const double* __restrict__ Ain
     R[e] = V[e] + U[e];
   }
   __syncthreads();
-  for (int k = 0; k < n; ++k) {
-    double best = -1.0;
-    int bi = k;
-    for (int i = k + t; i < n; i += kT) {
-      const double v = fabs(M[i + static_cast<int64_t>(n) * k]);
-      if (v > best) {
-        best = v;
-        bi = i;
+  if (n <= kSmallN) {
+    // LU with partial pivoting of M in LDS, then each column of R solved in
+    // registers by one wave (lane l holds rows l and l + 64; the value of
+    // row k is broadcast from its lane), so the sweeps need no block barrier
+    double* sM = smem;
+    for (int64_t e = t; e < nn; e += kT) sM[e] = M[e];
+    __syncthreads();
+    for (int k = 0; k < n; ++k) {
+      double best = -1.0;
+      int bi = k;
+      if (k + t < n) {
+        best = fabs(sM[k + t + n * k]);
+        bi = k + t;
       }
-    }
-    const int p = block_argmax(best, bi, red, redi);
-    if (p != k) {
-      for (int j = t; j < 2 * n; j += kT) {
-        double* X = (j < n) ? M : R;
-        const int jj = (j < n) ? j : j - n;
-        const int64_t a = k + static_cast<int64_t>(n) * jj, b = p + static_cast<int64_t>(n) * jj;
-        const double tmp = X[a];
-        X[a] = X[b];
-        X[b] = tmp;
+      const int p = block_argmax(best, bi, red, redi);
+      if (t == 0) spiv[k] = p;
+      if (p != k) {
+        for (int j = t; j < n; j += kT) {
+          const double tmp = sM[k + n * j];
+          sM[k + n * j] = sM[p + n * j];
+          sM[p + n * j] = tmp;
+        }
+        __syncthreads();
+      }
+      const double piv = sM[k + n * k];
+      for (int i = k + 1 + t; i < n; i += kT) sM[i + n * k] /= piv;
+      __syncthreads();
+      const int rows = n - k - 1;
+      for (int e = t; e < rows * rows; e += kT) {
+        const int i = k + 1 + e % rows, j = k + 1 + e / rows;
+        sM[i + n * j] -= sM[i + n * k] * sM[k + n * j];
       }
       __syncthreads();
     }
-    const double piv = M[k + static_cast<int64_t>(n) * k];
-    // multipliers stored below the diagonal of column k
-    for (int i = k + 1 + t; i < n; i += kT) M[i + static_cast<int64_t>(n) * k] /= piv;
-    __syncthreads();
-    const int rows = n - k - 1;
-    const int cols = (n - k - 1) + n;  // remaining columns of M, then all of R
-    for (int e = t; e < rows * cols; e += kT) {
-      const int i = k + 1 + e % rows;
-      const int jc = e / rows;
-      const double l = M[i + static_cast<int64_t>(n) * k];
-      if (jc < n - k - 1) {
-        const int j = k + 1 + jc;
-        M[i + static_cast<int64_t>(n) * j] -= l * M[k + static_cast<int64_t>(n) * j];
-      } else {
-        const int j = jc - (n - k - 1);
-        R[i + static_cast<int64_t>(n) * j] -= l * R[k + static_cast<int64_t>(n) * j];
+    // row i of the permuted system is row sperm[i] of the original one
+    if (t == 0) {
+      for (int i = 0; i < n; ++i) sperm[i] = i;
+      for (int k = 0; k < n; ++k) {
+        const int tmp = sperm[k];
+        sperm[k] = sperm[spiv[k]];
+        sperm[spiv[k]] = tmp;
       }
     }
     __syncthreads();
-  }
-  for (int k = n - 1; k >= 0; --k) {
-    const double piv = M[k + static_cast<int64_t>(n) * k];
-    for (int j = t; j < n; j += kT) R[k + static_cast<int64_t>(n) * j] /= piv;
-    __syncthreads();
-    for (int e = t; e < k * n; e += kT) {
-      const int i = e % k, j = e / k;
-      R[i + static_cast<int64_t>(n) * j] -= M[i + static_cast<int64_t>(n) * k] *
-                                            R[k + static_cast<int64_t>(n) * j];
+    const int lane = t & 63, wv = t >> 6;
+    for (int j = wv; j < n; j += kT / 64) {
+      double x0 = lane < n ? R[sperm[lane] + static_cast<int64_t>(n) * j] : 0.0;
+      double x1 = lane + 64 < n ? R[sperm[lane + 64] + static_cast<int64_t>(n) * j] : 0.0;
+      for (int k = 0; k < n - 1; ++k) {  // unit lower triangle
+        const double xk = __shfl(k < 64 ? x0 : x1, k & 63);
+        if (lane > k && lane < n) x0 -= sM[lane + n * k] * xk;
+        if (lane + 64 > k && lane + 64 < n) x1 -= sM[lane + 64 + n * k] * xk;
+      }
+      for (int k = n - 1; k >= 0; --k) {  // upper triangle
+        if (lane == (k & 63)) {
+          if (k < 64) x0 /= sM[k + n * k];
+          else x1 /= sM[k + n * k];
+        }
+        const double xk = __shfl(k < 64 ? x0 : x1, k & 63);
+        if (lane < k) x0 -= sM[lane + n * k] * xk;
+        if (lane + 64 < k) x1 -= sM[lane + 64 + n * k] * xk;
+      }
+      if (lane < n) R[lane + static_cast<int64_t>(n) * j] = x0;
+      if (lane + 64 < n) R[lane + 64 + static_cast<int64_t>(n) * j] = x1;
     }
     __syncthreads();
+  }
+  if (n > kSmallN) {
+    // larger matrices: the same elimination on M and R in global memory
+    for (int k = 0; k < n; ++k) {
+      double best = -1.0;
+      int bi = k;
+      for (int i = k + t; i < n; i += kT) {
+        const double v = fabs(M[i + static_cast<int64_t>(n) * k]);
+        if (v > best) {
+          best = v;
+          bi = i;
+        }
+      }
+      const int p = block_argmax(best, bi, red, redi);
+      if (p != k) {
+        for (int j = t; j < 2 * n; j += kT) {
+          double* X = (j < n) ? M : R;
+          const int jj = (j < n) ? j : j - n;
+          const int64_t a = k + static_cast<int64_t>(n) * jj, b = p + static_cast<int64_t>(n) * jj;
+          const double tmp = X[a];
+          X[a] = X[b];
+          X[b] = tmp;
+        }
+        __syncthreads();
+      }
+      const double piv = M[k + static_cast<int64_t>(n) * k];
+      // multipliers stored below the diagonal of column k
+      for (int i = k + 1 + t; i < n; i += kT) M[i + static_cast<int64_t>(n) * k] /= piv;
+      __syncthreads();
+      const int rows = n - k - 1;
+      const int cols = (n - k - 1) + n;  // remaining columns of M, then all of R
+      for (int e = t; e < rows * cols; e += kT) {
+        const int i = k + 1 + e % rows;
+        const int jc = e / rows;
+        const double l = M[i + static_cast<int64_t>(n) * k];
+        if (jc < n - k - 1) {
+          const int j = k + 1 + jc;
+          M[i + static_cast<int64_t>(n) * j] -= l * M[k + static_cast<int64_t>(n) * j];
+        } else {
+          const int j = jc - (n - k - 1);
+          R[i + static_cast<int64_t>(n) * j] -= l * R[k + static_cast<int64_t>(n) * j];
+        }
+      }
+      __syncthreads();
+    }
+    for (int k = n - 1; k >= 0; --k) {
+      const double piv = M[k + static_cast<int64_t>(n) * k];
+      for (int j = t; j < n; j += kT) R[k + static_cast<int64_t>(n) * j] /= piv;
+      __syncthreads();
+      for (int e = t; e < k * n; e += kT) {
+        const int i = e % k, j = e / k;
+        R[i + static_cast<int64_t>(n) * j] -= M[i + static_cast<int64_t>(n) * k] *
+                                              R[k + static_cast<int64_t>(n) * j];
+      }
+      __syncthreads();
+    }
   }
   // squarings: R <- R^2, s times (ping-pong between T2 and U)
   double* cur = R;
