@@ -125,7 +125,15 @@ ModeTile pick_tile(int form, int64_t Il, int64_t m, int64_t n, int64_t Ir) {
   if (form == FORM_F64) {
     t.bk = 16;
     if (n <= 16) { t.nb = 1; t.fb = 4; }
-    else if (n <= 32) { t.nb = 2; t.fb = 2; }
+    else if (n <= 32) {
+      t.nb = 2;
+      t.fb = 2;
+      // contractions of 17-24: 8-wide chunks waste less of the last chunk
+      if (m > 16 && m <= 24) {
+        t.bk = 8;
+        t.occ = 3;
+      }
+    }
     else {
       t.bk = 8;
       t.occ = 3;

@@ -93,9 +93,17 @@ bool strip_default(int form, int64_t Il, int64_t m, int64_t n, int64_t Ir, ModeT
   // workgroups per CU) beat the k-loop tile on the lead layout, and on the
   // inner layout only for small problems
   if (form == FORM_F64 && m > 32 && Il > 1 && (!sized || F > 65536)) return false;
+  // Inner layout, more than 64K fibers, 16 < n <= 64 and 16 < m <= 32
+  // (FP64) or 16 < m (FP32): the k-loop tiles measured 5-20 % faster (FP32
+  // m = 40-48: 30-50 %); for n <= 16 the strip stays ahead
+  if (sized && Il > 1 && F > 65536 && m > 16 && n > 16 && n <= 64 &&
+      (form == FORM_F32 || form == FORM_F64))
+    return false;
   // FP32 with m <= 16: the k-loop tile (one chunk, 16-byte loads) measured
-  // faster than the strip
-  if (form == FORM_F32 && m <= 16) return false;
+  // faster than the strip, except for m < 16 and n <= 16 over many fibers
+  // (strips 10-50 % faster from 512K fibers on)
+  if (form == FORM_F32 && m <= 16 && !(sized && m < 16 && n <= 16 && F >= 524288))
+    return false;
   const int kp = form == FORM_BF16X3 || form == FORM_BF16X6
                      ? (m <= 32 ? 32 : 64)
                      : (m <= 16 ? 16 : (m <= 32 ? 32 : (form == FORM_F64 && m <= 48 ? 48 : 64)));

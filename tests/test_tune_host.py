@@ -74,10 +74,24 @@ def test_set_lookup_list_clear(lib, L, tune):
     assert lib.kp_tune_count() == 0
     # short contractions default to a strip tile covering m; on small
     # problems with fewer rows per workgroup, so the workgroups fill the chip
-    tuned, tile = tune.lookup("f32", 7, 24, 40, 90000)
+    tuned, tile = tune.lookup("f32", 1, 24, 40, 630000)
     assert not tuned and tile[5] == 1 and tile[2] >= 24 and 16 * tile[0] >= 32
     tuned, tile = tune.lookup("f32", 7, 24, 40, 9)
     assert not tuned and tile[5] == 1 and tile[2] >= 24 and tile[0] == 1
+    # the inner layout over many fibers takes the k-loop tile for 16 < m
+    # (FP32) and 16 < m <= 32 (FP64) when 16 < n <= 64, with 8-wide chunks
+    # for FP64 m <= 24
+    assert tune.lookup("f32", 24, 24, 16, 13824)[1][5] == 1
+    assert tune.lookup("f32", 7, 24, 40, 90000) == (False, (4, 1, 16, 2, 1, 0))
+    assert tune.lookup("f32", 45, 45, 35, 45 ** 3) == (False, (4, 1, 16, 2, 1, 0))
+    assert tune.lookup("f64", 18, 18, 18, 18 ** 4) == (False, (2, 2, 8, 3, 1, 0))
+    assert tune.lookup("f64", 28, 28, 28, 28 ** 3) == (False, (2, 2, 16, 2, 1, 0))
+    assert tune.lookup("f64", 1, 18, 18, 18 ** 5)[1][5] == 1        # lead: a strip
+    assert tune.lookup("f64", 18, 18, 18, 100)[1][5] == 1           # small: a strip
+    # FP32 m < 16 over many fibers: the 16-long strip
+    assert tune.lookup("f32", 14, 14, 14, 14 ** 4) == (False, (1, 2, 16, 0, 0, 1))
+    assert tune.lookup("f32", 14, 14, 14, 14 ** 3)[1][5] == 0
+    assert tune.lookup("f32", 16, 16, 16, 16 ** 4)[1][5] == 0
     tune.set_tile("f32", 7, 24, 40, 9, (1, 2, 32, 0, 0, 1))
     assert tune.lookup("f32", 7, 24, 40, 9) == (True, (1, 2, 32, 0, 0, 1))
     tune.clear()
