@@ -99,6 +99,17 @@ def load_traffic(per_launch_units):
     return rec.get("hbm_bytes_per_launch")
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:  # pragma: no cover
+        pass
+    return "unknown"
+
+
 def cpu_baseline(T, Ls, flops, budget_s=12.0):
     import oracle
     try:
@@ -115,7 +126,7 @@ def cpu_baseline(T, Ls, flops, budget_s=12.0):
         if el > budget_s or reps >= 2000:
             break
     return {"value": flops * reps / el / 1e12, "unit": "TFLOP/s", "cores": int(threads),
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": cpu_model(),
             "sample": f"full cube200 Tucker operator (8M entries, 9.6 GFLOP), {reps} "
                       f"repetitions in {el:.1f} s, numpy float64"}
 
@@ -197,7 +208,9 @@ def main():
         for _ in range(args.warmup):
             S = kp.tucker(Td, Lds, prec=prec)
         torch.cuda.synchronize()
-        err = float(np.abs(S.double().cpu().numpy() - ref).max() / np.abs(ref).max())
+        got = S.double().cpu().numpy()
+        err = float(np.abs(got - ref).max() / np.abs(ref).max())
+        err_fro = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
         # timed region: K full Tucker steps, events on the launch stream
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
         torch.cuda.synchronize()
@@ -230,6 +243,13 @@ def main():
         mfma_tflops = tflops * (1 if prec == "native" else int(prec[-1]))
         hbm_min_bytes = (T.size + S.numel()) * Td.element_size() + \
             sum(L.size for L in Ls) * Td.element_size()
+        # roofline of the form: useful-flop peak (the split forms issue S
+        # products per useful one) against the unfused traffic (every mode
+        # reads and writes the whole tensor) at 8 TB/s
+        unfused_bytes = 3 * (T.size + S.numel()) * Td.element_size() + \
+            sum(L.size for L in Ls) * Td.element_size()
+        useful_peak = peak / (1 if prec == "native" else int(prec[-1]))
+        roof_tflops = min(useful_peak, flops / unfused_bytes * HBM_PEAK_GBS / 1e3)
         results[name] = {
             "tflops": round(tflops, 3),
             "ms_per_step": round(ms, 5),
@@ -238,7 +258,10 @@ def main():
             "mfma_issued_tflops": round(mfma_tflops, 3),
             "peak_tflops": peak,
             "hbm_min_gbs": round(hbm_min_bytes / (ms * 1e-3) / 1e9, 1),
+            "roofline_tflops": round(roof_tflops, 1),
+            "frac_of_roofline": round(tflops / roof_tflops, 4),
             "rel_err_maxnorm": err,
+            "rel_err_frobenius": err_fro,
             "meets_1e-6": err <= 1e-6,
             "mode_ms": {str(k): round(v, 5) for k, v in per_mode.items()},
         }
