@@ -74,6 +74,38 @@ def test_mump_accumulate(kp, dt, prec):
     assert rel_max(out.double().cpu().numpy(), ref) < tol
 
 
+# Views whose default tile comes from the size rules (inner layout over more
+# than 64K fibers, short contractions): torch shape (Ir, m, Il), factor
+# (n, m), mode 2; with the tile kind the default must pick (0 k-loop,
+# 1 strip) and a view a strip covers that stays on it (lead layout)
+RULE_CASES = [
+    ("f32", (3000, 24, 24), 40, 0),     # FP32 16 < m, 16 < n <= 64: k-loop
+    ("f32", (1500, 45, 45), 35, 0),     # FP32 m = 45 (the Runge modes)
+    ("f64", (4000, 18, 18), 18, 0),     # FP64 16 < m <= 24: 8-wide chunks
+    ("f64", (3000, 28, 28), 28, 0),     # FP64 24 < m <= 32
+    ("f32", (37500, 14, 14), 14, 1),    # FP32 m < 16 over >= 512K fibers: strip
+    ("f32", (13824, 24, 16), 16, 1),    # FP32 n <= 16: the strip stays
+    ("f64", (50000, 18, 1), 18, 1),     # lead layout: the strip stays
+]
+
+
+@pytest.mark.parametrize("case", range(len(RULE_CASES)))
+def test_mump_default_tile_rules(kp, case):
+    dt, shape, n, kind = RULE_CASES[case]
+    Ir, m, Il = shape
+    rng = np.random.default_rng(300 + case)
+    T = rng.standard_normal(shape)
+    L = rng.standard_normal((n, m))
+    form = "f64" if dt == "f64" else "f32"
+    assert kp.tune.lookup(form, Il, m, n, Ir)[1][5] == kind
+    say("mump default rule", dt, shape, n, "kind", kind)
+    S, T64, L64 = run_mump(kp, T, L, 2, dt, "native")
+    ref = oracle.mump(T64, L64, 2)
+    factors = [None, L64, None]
+    bound = chain_bound(T64, factors, "native", DT[dt])
+    assert np.all(np.abs(S - ref) <= bound), float(np.max(np.abs(S - ref) / bound))
+
+
 def test_mump_empty_contraction_gives_zeros(kp):
     # m_mu = 0: every output entry is an empty sum.
     T = np.zeros((3, 0, 4))
