@@ -106,6 +106,49 @@ def test_mump_default_tile_rules(kp, case):
     assert np.all(np.abs(S - ref) <= bound), float(np.max(np.abs(S - ref) / bound))
 
 
+# Tensors past 2 GiB: each launch addresses its operands with 32-bit byte
+# offsets, so the product is split along the outer index b into pieces below
+# 2^31 bytes. torch shape (Ir, m, Il), factor (n, m), mode 2, and the first
+# b of the second piece: floor((2^31 - 1) / (Il * max(m, n) * bytes)).
+BIG_CASES = [
+    ("f64", (1500, 200, 1000), 150),      # inner, k-loop tile
+    ("f64", (1_500_000, 200, 1), 150),    # lead, k-loop tile
+    ("f64", (8_000_000, 40, 1), 40),      # lead, 48-long strip
+    ("f32", (3000, 200, 1000), 100),      # inner, FP32 k-loop tile
+]
+
+
+@pytest.mark.parametrize("case", range(len(BIG_CASES)))
+def test_mump_beyond_2gib_sampled(kp, case):
+    from gpu_util import unit_error
+    dt, (Ir, m, Il), n = BIG_CASES[case]
+    es = 8 if dt == "f64" else 4
+    assert Ir * m * Il * es > 2 ** 31
+    per = (2 ** 31 - 1) // (Il * max(m, n) * es)
+    assert 0 < per < Ir
+    say("mump beyond 2 GiB", dt, (Ir, m, Il), n, "piece", per)
+    g = torch.Generator(device="cuda").manual_seed(500 + case)
+    X = torch.randn((Ir, m, Il), dtype=DT[dt], device="cuda", generator=g)
+    L = torch.randn((n, m), dtype=DT[dt], device="cuda", generator=g)
+    Y = kp.mump(X, L, 2)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(600 + case)
+    bs = np.unique(np.concatenate([[0, per - 1, per, per + 1, Ir - 1],
+                                   rng.integers(0, Ir, 40)]))
+    As = np.unique(np.concatenate([[0, Il - 1], rng.integers(0, Il, 8)]))
+    bi = torch.as_tensor(bs, device="cuda")
+    ai = torch.as_tensor(As, device="cuda")
+    xs = X[bi][:, :, ai].double().cpu().numpy()      # (nb, m, na)
+    ys = Y[bi][:, :, ai].double().cpu().numpy()      # (nb, n, na)
+    L64 = L.double().cpu().numpy()
+    ref = np.einsum("ij,bja->bia", L64, xs)
+    bound = 2 * unit_error("native", DT[dt], m) * np.einsum("ij,bja->bia", np.abs(L64),
+                                                               np.abs(xs)) + 1e-300
+    assert np.all(np.abs(ys - ref) <= bound), float(np.max(np.abs(ys - ref) / bound))
+    del X, Y
+    torch.cuda.empty_cache()
+
+
 def test_mump_empty_contraction_gives_zeros(kp):
     # m_mu = 0: every output entry is an empty sum.
     T = np.zeros((3, 0, 4))
