@@ -117,6 +117,13 @@ const Variant* find_variant(int form, const ModeTile& t) {
 // BF16 split forms 4 blocks (BF16x6 with two chunks in flight). Short
 // contractions (m <= 64; FP64: m <= 32, or m <= 64 on the lead layout)
 // take strip tiles.
+// 16-row blocks left empty in the last n tile when n is covered by tiles of
+// nb blocks.
+int64_t idle_blocks(int64_t n, int nb) {
+  const int64_t b = (n + 15) / 16;
+  return nb * ((b + nb - 1) / nb) - b;
+}
+
 ModeTile pick_tile(int form, int64_t Il, int64_t m, int64_t n, int64_t Ir) {
   ModeTile t{};
   if (strip_default(form, Il, m, n, Ir, &t)) return t;
@@ -144,13 +151,27 @@ ModeTile pick_tile(int form, int64_t Il, int64_t m, int64_t n, int64_t Ir) {
         t.occ = 2;
         t.pf = 2;
       }
+      // n > 184 whose last 7-block tile would be at least 4 blocks emptier
+      // than with 4-block tiles (n = 240, 256, 352, 384: 8-14 % faster)
+      if (n > 184 && idle_blocks(n, 7) - idle_blocks(n, 4) >= 4) {
+        t.nb = 4;
+        t.bk = 16;
+        t.occ = 2;
+        t.pf = 2;
+      }
     }
   } else if (form == FORM_F32) {
     t.bk = 16;
     if (n <= 16) { t.nb = 1; t.fb = 4; }
     else if (n <= 32) { t.nb = 2; t.fb = 2; }
     else if (n <= 64) { t.nb = 4; t.fb = 1; }
-    else { t.nb = n <= 128 ? 8 : (n <= 184 ? 4 : 7); t.fb = 1; t.pf = 2; }
+    else {
+      t.nb = n <= 128 ? 8 : (n <= 184 ? 4 : 7);
+      t.fb = 1;
+      t.pf = 2;
+      // the same for 8-block tiles (n = 240, 256, 352, 384: 10-18 % faster)
+      if (n > 184 && idle_blocks(n, 7) - idle_blocks(n, 8) >= 4) t.nb = 8;
+    }
   } else {
     t.bk = 32;
     if (n <= 16) { t.nb = 1; t.fb = 4; }

@@ -108,6 +108,14 @@ def test_set_lookup_list_clear(lib, L, tune):
     # small k-loop problems (64 < n <= 184) take smaller tiles
     assert tune.lookup("f64", 1, 128, 128, 128 * 128)[1][:3] == (4, 1, 16)
     assert tune.lookup("f64", 1, 200, 200, 200 * 200)[1][:3] == (7, 1, 8)
+    # n > 184: shorter tiles where 7-block tiles would leave the last one
+    # mostly empty (16-row blocks: 15, 16, 22, 24 for n = 240, 256, 352, 384)
+    for n in (240, 256, 352, 384):
+        assert tune.lookup("f64", n, n, n, n)[1] == (4, 1, 16, 2, 2, 0)
+        assert tune.lookup("f32", n, n, n, n)[1] == (8, 1, 16, 2, 2, 0)
+    for n in (200, 272, 288, 320, 324):
+        assert tune.lookup("f64", n, n, n, n)[1][0] == 7
+        assert tune.lookup("f32", n, n, n, n)[1][0] == 7
     tune.set_tile("f64", 40, 200, 200, 200, (4, 1, 16))
     tuned, tile = tune.lookup("f64", 40, 200, 200, 200)
     assert tuned and tile[:3] == (4, 1, 16) and tile[3] > 0 and tile[4:] == (1, 0)  # resolved
