@@ -44,8 +44,8 @@ int64_t count_of(const int64_t* dims, int d) {
 }
 
 // The factor applied at complex mode k: L, or its transpose for the
-// conjugate-transpose form (the sign of the imaginary part is applied by
-// the combining pass).
+// conjugate-transpose form (the sign of the imaginary part is applied in
+// the epilogue of the imaginary-part product).
 kp_matrix applied(const kp_matrix& L, int conj) {
   if (!conj) return L;
   kp_matrix t = L;
