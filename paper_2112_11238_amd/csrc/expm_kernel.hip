@@ -12,6 +12,9 @@
 // synchronises with the host, so every step (norm, scaling, products, the
 // LU solve with partial pivoting, the squarings) runs inside one persistent
 // workgroup per matrix; `count` matrices run side by side in one launch.
+// The products run on the FP64 matrix cores; for n <= 128 the LU factors of
+// q(B) stay in LDS and each column of the right-hand side is solved in
+// registers by one wave.
 #include "kp.h"
 
 #include <math.h>
