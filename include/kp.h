@@ -144,7 +144,11 @@ int kp_kronsum(const kp_tensor* T, const kp_matrix* const A[], kp_tensor* S, int
  * P_k = T x_1 L_1 ... x_k L_k for k = 1..d-1 in definition order, packed one
  * after another as column-major tensors (cache_bytes >= kp_tucker_cache_size);
  * kp_tucker_backward can reuse them. Requesting the cache forces the
- * definition order 1..d. */
+ * definition order 1..d.
+ * Errors: KP_ERR_SHAPE / KP_ERR_DTYPE / KP_ERR_NULL as kp_mump;
+ * KP_ERR_WORKSPACE if ws (or the cache) is missing or too small;
+ * KP_ERR_ALIAS if S overlaps T or a factor, if the part of ws the call uses
+ * overlaps T, S or a factor, or if the cache overlaps T, S, a factor or ws. */
 size_t kp_tucker_workspace(const kp_tensor* T, const kp_matrix* const* L, int prec);
 /* The order kp_tucker applies the non-identity factors in (without a cache):
  * order[0..*count-1] receives 1-based modes. Host-only query. */
@@ -189,7 +193,10 @@ int kp_tucker_complex(const kp_tensor* T, const kp_matrix* const* Lre,
  * dT may be NULL, and any dL[k] may be NULL, to skip that output. The dL[k]
  * are written with their own strides (dtype of T). `cache` is the forward
  * cache written by kp_tucker (or NULL: the P_k are recomputed).
- * Every L[k] must be non-NULL here. ws_bytes >= kp_tucker_backward_workspace. */
+ * Every L[k] must be non-NULL here. ws_bytes >= kp_tucker_backward_workspace.
+ * Errors: as kp_tucker; KP_ERR_ALIAS if an output (dT, a dL[k]) overlaps an
+ * input (G, T, a factor, the cache), ws or another output, or if ws overlaps
+ * G, T, a factor or the cache. */
 size_t kp_tucker_backward_workspace(const kp_tensor* T, const kp_matrix* const* L,
                                     int prec);
 int kp_tucker_backward(const kp_tensor* G, const kp_tensor* T,

@@ -410,13 +410,26 @@ int kp_tucker(const kp_tensor* T, const kp_matrix* const* L, kp_tensor* S, int p
 
   ChainPlan p;
   make_chain(*T, L, cache != nullptr, &p);
-  if (cache && cache_bytes < cache_bytes_for(*T, L)) return KP_ERR_WORKSPACE;
+  const size_t need_cache = cache ? cache_bytes_for(*T, L) : 0;
+  if (cache && cache_bytes < need_cache) return KP_ERR_WORKSPACE;
   size_t off1 = 0, need = 0;
   if (!cache) {
     chain_ws(p, es, &off1, &need);
     if (need > 0 && (!ws || ws_bytes < need)) return KP_ERR_WORKSPACE;
-    if (need > 0 && overlaps(ws, need, S->data, sb)) return KP_ERR_ALIAS;
   }
+  // Buffers the chain writes (the used part of ws, the cache) must not
+  // overlap anything it reads or writes elsewhere.
+  const size_t Tb = static_cast<size_t>(numel(*T)) * es;
+  auto hits_inputs = [&](const void* buf, size_t bytes) {
+    if (overlaps(buf, bytes, T->data, Tb) || overlaps(buf, bytes, S->data, sb)) return true;
+    for (int k = 0; k < T->d; ++k)
+      if (L[k] && overlaps(buf, bytes, L[k]->data, matrix_span_bytes(*L[k]))) return true;
+    return false;
+  };
+  if (need > 0 && hits_inputs(ws, need)) return KP_ERR_ALIAS;
+  if (need_cache > 0 &&
+      (hits_inputs(cache, need_cache) || overlaps(cache, need_cache, ws, ws ? ws_bytes : 0)))
+    return KP_ERR_ALIAS;
   const int form = form_of(prec, T->dtype);
   if (numel(*S) == 0) return KP_OK;
   if (p.count == 0) {
@@ -523,11 +536,25 @@ int kp_tucker_backward(const kp_tensor* G, const kp_tensor* T, const kp_matrix* 
       if (!dL[k]) continue;
       const size_t lb = matrix_span_bytes(*dL[k]);
       if (overlaps(dL[k]->data, lb, T->data, Tb) || overlaps(dL[k]->data, lb, G->data, Gb) ||
-          overlaps(dL[k]->data, lb, ws, b.total))
+          overlaps(dL[k]->data, lb, ws, b.total) ||
+          overlaps(dL[k]->data, lb, cache, have_cache ? need_cache : 0))
         return KP_ERR_ALIAS;
-      for (int j = 0; j < d; ++j)
+      if (dT && overlaps(dL[k]->data, lb, dT->data, static_cast<size_t>(numel(*dT)) * es))
+        return KP_ERR_ALIAS;
+      for (int j = 0; j < d; ++j) {
         if (overlaps(dL[k]->data, lb, L[j]->data, matrix_span_bytes(*L[j]))) return KP_ERR_ALIAS;
+        if (j != k && dL[j] && overlaps(dL[k]->data, lb, dL[j]->data, matrix_span_bytes(*dL[j])))
+          return KP_ERR_ALIAS;
+      }
     }
+  }
+  // the workspace is written: it must not overlap an input or the cache
+  if (b.total > 0) {
+    if (overlaps(ws, b.total, T->data, Tb) || overlaps(ws, b.total, G->data, Gb) ||
+        overlaps(ws, b.total, cache, have_cache ? need_cache : 0))
+      return KP_ERR_ALIAS;
+    for (int k = 0; k < d; ++k)
+      if (overlaps(ws, b.total, L[k]->data, matrix_span_bytes(*L[k]))) return KP_ERR_ALIAS;
   }
   const int form = form_of(prec, T->dtype);
   char* wsb = static_cast<char*>(ws);

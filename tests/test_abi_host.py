@@ -220,6 +220,56 @@ def test_backward_argument_errors(lib, L):
 
 
 @no_device
+def test_tucker_workspace_and_cache_alias_errors(lib, L):
+    # T at FAKE (4*5*6 floats), factors at FAKE+0x100000 (matrix default),
+    # S at FAKE+0x300000; a buffer the call writes (ws, cache) may overlap none
+    # of them, nor each other.
+    T = tensor(L, [4, 5, 6], dtype=1)
+    Ms = [matrix(L, 3, 4, 1, data=FAKE + 0x100000), matrix(L, 2, 5, 1, data=FAKE + 0x110000),
+          matrix(L, 5, 6, 1, data=FAKE + 0x120000)]
+    S = tensor(L, [3, 2, 5], dtype=1, data=FAKE + 0x300000)
+    arr = mlist(L, Ms)
+    need = lib.kp_tucker_workspace(ctypes.byref(T), arr, 0)
+    cb = lib.kp_tucker_cache_size(ctypes.byref(T), arr)
+    ws_ok, cache_ok = FAKE + 0x900000, FAKE + 0xA00000
+
+    def call(ws=ws_ok, nb=need, cache=None, cbytes=0):
+        return lib.kp_tucker(ctypes.byref(T), arr, ctypes.byref(S), 0, ws, nb, cache, cbytes,
+                             None)
+    for bad in (FAKE + 16, FAKE + 0x300000 + 8, FAKE + 0x110000):    # T, S, a factor
+        assert call(ws=bad) == -6, hex(bad)
+        assert call(ws=None, nb=0, cache=bad, cbytes=cb) == -6, hex(bad)
+    assert call(ws=cache_ok + 64, nb=need, cache=cache_ok, cbytes=cb) == -6   # cache vs ws
+
+
+@no_device
+def test_backward_cache_and_output_alias_errors(lib, L):
+    T = tensor(L, [4, 5], dtype=0)
+    G = tensor(L, [3, 2], dtype=0, data=FAKE + 0x400000)
+    Ms = mlist(L, [matrix(L, 3, 4, data=FAKE + 0x100000), matrix(L, 2, 5, data=FAKE + 0x110000)])
+    need = lib.kp_tucker_backward_workspace(ctypes.byref(T), Ms, 0)
+    cb = lib.kp_tucker_cache_size(ctypes.byref(T), Ms)
+    ws, cache = FAKE + 0x900000, FAKE + 0xA00000
+    dT = tensor(L, [4, 5], data=FAKE + 0x500000)
+
+    def dl(a0, a1):
+        return mlist(L, [matrix(L, 3, 4, data=a0), matrix(L, 2, 5, data=a1)])
+    good = dl(FAKE + 0x600000, FAKE + 0x610000)
+
+    def call(w=ws, c=cache, d_T=dT, d_L=good):
+        return lib.kp_tucker_backward(ctypes.byref(G), ctypes.byref(T), Ms, c, cb,
+                                      ctypes.byref(d_T) if d_T is not None else None, d_L, 0,
+                                      w, need, None)
+    # a factor gradient written over the cache, dT, or another gradient
+    assert call(d_L=dl(cache + 8, FAKE + 0x610000)) == -6
+    assert call(d_L=dl(FAKE + 0x500000, FAKE + 0x610000)) == -6
+    assert call(d_L=dl(FAKE + 0x600000, FAKE + 0x600008)) == -6
+    # the workspace over an input or the cache
+    for bad in (FAKE + 8, FAKE + 0x400000, FAKE + 0x110000, cache + 16):
+        assert call(w=bad) == -6, hex(bad)
+
+
+@no_device
 def test_expm_argument_errors(lib):
     ws = lib.kp_expm_workspace(128, 3)
     assert ws == 8 * 128 * 128 * 3 * 8
