@@ -33,7 +33,7 @@ from .tucker import (vec, unvec, mumat, mump, tucker, nested, tucker_entry,
 from .factors import (fd_laplacian_dirichlet, expm_fd_laplacian_dirichlet,
                       dst1_eigenpairs, chebyshev_nodes, chebyshev_weights,
                       lagrange_matrix, runge)
-from .grad import tucker_vjp, central_fd_directional
+from .grad import tucker_vjp, factor_gradient_column, central_fd_directional
 from .complex_tucker import zmump, ztucker, cttucker, dft_matrix
 from .semilinear import (tridiag, tridiag_inverse, pcg, semilinear_grid, semilinear_u0,
                          semilinear_laplacian_u0, semilinear_phi, semilinear_rhs,
@@ -44,7 +44,7 @@ __all__ = [
     "kron", "kronsum", "kronsumv",
     "fd_laplacian_dirichlet", "expm_fd_laplacian_dirichlet", "dst1_eigenpairs",
     "chebyshev_nodes", "chebyshev_weights", "lagrange_matrix", "runge",
-    "tucker_vjp", "central_fd_directional",
+    "tucker_vjp", "factor_gradient_column", "central_fd_directional",
     "zmump", "ztucker", "cttucker", "dft_matrix",
     "tridiag", "tridiag_inverse", "pcg", "semilinear_grid", "semilinear_u0",
     "semilinear_laplacian_u0", "semilinear_phi", "semilinear_rhs", "semilinear_factors",

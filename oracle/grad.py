@@ -39,6 +39,26 @@ def tucker_vjp(T, Ls, G):
     return dT, dLs
 
 
+def factor_gradient_column(T, Ls, G, mu, j):
+    """Column j (0-based) of dL_mu for S = tucker(T, Ls) and cotangent G.
+
+    With Z_mu = T multiplied by every factor except L_mu, dL_mu = G^(mu)
+    (Z_mu^(mu))^T, so its column j only involves the mu-fibers' entry j of
+    Z_mu, i.e. the slice of T at j_mu = j multiplied by the other factors
+    (each mu-mode product acts on the other modes only, Sec. 2). Cost: about
+    1/m_mu of a full Tucker operator; used to sample gradients of tensors too
+    large for :func:`tucker_vjp`. Pinned against central differences and
+    against :func:`tucker_vjp`."""
+    T = np.asarray(T, dtype=np.float64)
+    G = np.asarray(G, dtype=np.float64)
+    d = T.ndim
+    Z = np.take(T, [j], axis=mu - 1)
+    for nu in range(1, d + 1):
+        if nu != mu:
+            Z = mump(Z, Ls[nu - 1], nu)
+    return (mumat(G, mu) @ mumat(Z, mu).T)[:, 0]
+
+
 def central_fd_directional(f, x, v, h):
     """(f(x + h v) - f(x - h v)) / (2h): the central difference of the scalar
     function f at x along direction v."""

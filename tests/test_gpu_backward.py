@@ -214,3 +214,98 @@ def test_interp6d_backward_full_size_rank1_cotangent(kp, prec):
         g = dLs[k].double().cpu().numpy()
         say("dL", k, "rel err", rel_max(g, rL[k]))
         assert np.all(np.abs(g - rL[k]) <= 2 * coef * aL[k] + 1e-300), k
+
+
+# ---------------------------------------------------------------------------
+# Directional central differences at the full interp6d size (d = 6, T 16^6,
+# 24 x 16 Lagrange factors) with a general cotangent G (24^6, standard
+# normal): the loss f(T, L) = <G, tucker(T, L)> is evaluated by the FP64
+# oracle at theta +- h v for 16 random directions v, and compared with the
+# directional derivative <dT, v_T> + sum_mu <dL_mu, v_mu> of the GPU gradient.
+# Each block of v is scaled to the norm of its parameter block (every block
+# then contributes to the derivative on the same scale), so |v| = |theta| and
+# the step h = 1e-4 |theta| / |v| is 1e-4. f is a polynomial of degree 7 along
+# v, so the central difference's truncation error is about 35 h^2 relative.
+# ---------------------------------------------------------------------------
+FD_DIRECTIONS = 16
+FD_STEP = 1e-4
+
+
+def _fd_direction(k, T64, L64):
+    rng = np.random.default_rng(4600 + k)
+    VT = rng.standard_normal(T64.shape)
+    VT *= np.linalg.norm(T64) / np.linalg.norm(VT)
+    VL = []
+    for L in L64:
+        V = rng.standard_normal(L.shape)
+        VL.append(V * (np.linalg.norm(L) / np.linalg.norm(V)))
+    return VT, VL
+
+
+@pytest.fixture(scope="module")
+def interp6d_fd():
+    T, Ls = kp_workloads.interp6d(seed=0)
+    T64 = cast64(T, torch.float32)
+    L64 = [cast64(L, torch.float32) for L in Ls]
+    G = np.random.default_rng(4500).standard_normal((24,) * 6).astype(np.float32)
+    Gf = np.asfortranarray(G.astype(np.float64))
+
+    def loss(Tx, Lx):
+        S = oracle.tucker(Tx, Lx)
+        return float(np.dot(Gf.reshape(-1, order="F"), S.reshape(-1, order="F")))
+
+    say("interp6d directional FD: oracle evaluations")
+    fd = []
+    for k in range(FD_DIRECTIONS):
+        VT, VL = _fd_direction(k, T64, L64)
+        h = FD_STEP
+        fp = loss(T64 + h * VT, [L + h * V for L, V in zip(L64, VL)])
+        fm = loss(T64 - h * VT, [L - h * V for L, V in zip(L64, VL)])
+        fd.append((fp - fm) / (2 * h))
+        say("direction", k, "done")
+    del Gf
+    return T, Ls, G, T64, L64, fd
+
+
+# 32 FP64 oracle evaluations of a 24^6 output (a few seconds each on the
+# host) run in the module fixture: the limit covers that CPU work.
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("prec", ["native", "bf16x6"])
+def test_interp6d_backward_directional_fd(kp, interp6d_fd, prec):
+    T, Ls, G, T64, L64, fd = interp6d_fd
+    say("interp6d backward vs directional FD", prec)
+    Td = to_dev(T, torch.float32)
+    Lds = [to_dev(L, torch.float32) for L in Ls]
+    dT, dLs = kp.tucker_backward(to_dev(G, torch.float32), Td, Lds, prec)
+    torch.cuda.synchronize()
+    gT = dT.double().cpu().numpy()
+    gL = [x.double().cpu().numpy() for x in dLs]
+    del dT, dLs, Td
+    worst = 0.0
+    for k in range(FD_DIRECTIONS):
+        VT, VL = _fd_direction(k, T64, L64)
+        dd = float(np.vdot(gT, VT)) + sum(float(np.vdot(g, V)) for g, V in zip(gL, VL))
+        rel = abs(dd - fd[k]) / abs(fd[k])
+        worst = max(worst, rel)
+        assert rel <= 1e-5, (k, dd, fd[k], rel)
+    say("worst relative difference", worst)
+
+
+@pytest.mark.timeout(600)
+def test_interp6d_backward_general_cotangent_vs_oracle(kp, interp6d_fd):
+    # The FP32 gradient against the oracle's analytic gradient at full size,
+    # max-norm relative <= 1e-6 (the FP32 target).
+    T, Ls, G, T64, L64, _ = interp6d_fd
+    say("interp6d backward, general cotangent, vs oracle")
+    Td = to_dev(T, torch.float32)
+    Lds = [to_dev(L, torch.float32) for L in Ls]
+    dT, dLs = kp.tucker_backward(to_dev(G, torch.float32), Td, Lds)
+    torch.cuda.synchronize()
+    rT, rL = oracle.tucker_vjp(T64, L64, G.astype(np.float64))
+    err = rel_max(dT.double().cpu().numpy(), rT)
+    say("dT rel err", err)
+    assert err <= 1e-6
+    for k in range(6):
+        e = rel_max(dLs[k].double().cpu().numpy(), rL[k])
+        say("dL", k, "rel err", e)
+        assert e <= 1e-6, k

@@ -101,7 +101,9 @@ def test_heat128_pipeline(kp, dt, prec):
     err = rel_max(got, ref)
     say("rel err", err)
     if dt == "f64":
-        assert err < 1e-12
+        # the FP64 target; the GPU factors themselves differ from the closed
+        # form by about 1e-14
+        assert err < 1e-13
     else:
         bound = chain_bound(V64, L64, prec, tdt)
         assert np.all(np.abs(got - ref) <= bound)

@@ -57,7 +57,8 @@ def test_runge5d_errors_match_printed(kp, m, printed):
 
 
 @pytest.mark.parametrize("d,n", kp_workloads.codeval_shapes())
-@pytest.mark.parametrize("dt,prec", [("f64", "native"), ("f32", "bf16x3")])
+@pytest.mark.parametrize("dt,prec", [("f64", "native"), ("f32", "native"), ("f32", "bf16x3"),
+                                     ("f32", "bf16x6")])
 def test_codeval_shapes_sampled(kp, d, n, dt, prec):
     T, Ls = kp_workloads.cube(seed=n, n=n, d=d)
     tdt = torch.float64 if dt == "f64" else torch.float32

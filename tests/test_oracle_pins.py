@@ -399,3 +399,28 @@ def test_gradient_q_p_form_agrees():
         dL = oracle.mumat(Q, mu) @ oracle.mumat(P[mu - 1], mu).T
         assert rel(dL, dLs[mu - 1]) < 1e-13
         Q = oracle.mump(Q, Ls[mu - 1].T, mu)
+
+
+def test_factor_gradient_column_matches_central_differences():
+    # every entry of the sampled column by central differences of the loss
+    # <G, tucker(T, Ls)> in the one factor entry, and the column against the
+    # full gradient
+    rng = np.random.default_rng(17)
+    m, n = (3, 4, 2, 3), (2, 3, 4, 2)
+    T, Ls = rand_problem(rng, m, n)
+    G = rng.standard_normal(n)
+    _, dLs = oracle.tucker_vjp(T, Ls, G)
+    for mu in range(1, 5):
+        for j in range(m[mu - 1]):
+            col = oracle.factor_gradient_column(T, Ls, G, mu, j)
+            assert rel(col, dLs[mu - 1][:, j]) < 1e-13
+
+            def loss(Lm, mu=mu):
+                L2 = list(Ls)
+                L2[mu - 1] = Lm
+                return float(np.sum(G * oracle.nested(T, L2)))
+            for i in range(n[mu - 1]):
+                E = np.zeros_like(Ls[mu - 1])
+                E[i, j] = 1.0
+                fd = oracle.central_fd_directional(loss, Ls[mu - 1], E, 1e-5)
+                assert fd == pytest.approx(col[i], rel=1e-7, abs=1e-9)
