@@ -269,26 +269,39 @@ def interp6d_fd():
 
 # 32 FP64 oracle evaluations of a 24^6 output (a few seconds each on the
 # host) run in the module fixture: the limit covers that CPU work.
+#
+# The directional derivative is a sum of one term per parameter block,
+# <dT, v_T> + sum_mu <dL_mu, v_mu>, and for a random direction these terms
+# cancel (direction 13: terms of up to 1.8e4 summing to 2.6e3). The FP64
+# gradient is held to 1e-5 of |FD| itself. An FP32 gradient carries FP32
+# rounding in every block term (the factor gradients are sums of 16^5 * 24
+# products), so its difference from the FD is measured against the size of
+# the terms, sum_b |<grad_b, v_b>|, at the same 1e-5; its distance to |FD|
+# is reported beside it.
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("prec", ["native", "bf16x6"])
-def test_interp6d_backward_directional_fd(kp, interp6d_fd, prec):
+@pytest.mark.parametrize("dt,prec", [("f64", "native"), ("f32", "native"), ("f32", "bf16x6")])
+def test_interp6d_backward_directional_fd(kp, interp6d_fd, dt, prec):
     T, Ls, G, T64, L64, fd = interp6d_fd
-    say("interp6d backward vs directional FD", prec)
-    Td = to_dev(T, torch.float32)
-    Lds = [to_dev(L, torch.float32) for L in Ls]
-    dT, dLs = kp.tucker_backward(to_dev(G, torch.float32), Td, Lds, prec)
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    say("interp6d backward vs directional FD", dt, prec)
+    # T64, L64 hold the FP32-rounded inputs (exact in either dtype)
+    Td = to_dev(T64, tdt)
+    Lds = [to_dev(L, tdt) for L in L64]
+    dT, dLs = kp.tucker_backward(to_dev(G, tdt), Td, Lds, prec)
     torch.cuda.synchronize()
     gT = dT.double().cpu().numpy()
     gL = [x.double().cpu().numpy() for x in dLs]
     del dT, dLs, Td
-    worst = 0.0
+    worst = worst_fd = 0.0
     for k in range(FD_DIRECTIONS):
         VT, VL = _fd_direction(k, T64, L64)
-        dd = float(np.vdot(gT, VT)) + sum(float(np.vdot(g, V)) for g, V in zip(gL, VL))
-        rel = abs(dd - fd[k]) / abs(fd[k])
-        worst = max(worst, rel)
-        assert rel <= 1e-5, (k, dd, fd[k], rel)
-    say("worst relative difference", worst)
+        terms = [float(np.vdot(gT, VT))] + [float(np.vdot(g, V)) for g, V in zip(gL, VL)]
+        dd = sum(terms)
+        rel_fd = abs(dd - fd[k]) / abs(fd[k])
+        rel = rel_fd if dt == "f64" else abs(dd - fd[k]) / sum(abs(x) for x in terms)
+        worst, worst_fd = max(worst, rel), max(worst_fd, rel_fd)
+        assert rel <= 1e-5, (k, dd, fd[k], rel, rel_fd)
+    say("worst relative difference", worst, "(to |FD|:", worst_fd, ")")
 
 
 @pytest.mark.timeout(600)
