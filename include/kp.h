@@ -72,7 +72,9 @@ typedef enum {
   KP_ERR_ALIAS = -6,     /* an output overlaps an input */
   KP_ERR_WORKSPACE = -7, /* workspace missing or smaller than required */
   KP_ERR_HIP = -8,       /* a HIP launch failed; see kp_last_hip_error() */
-  KP_ERR_VALUE = -9      /* a scalar argument is out of range */
+  KP_ERR_VALUE = -9,     /* a scalar argument is out of range */
+  KP_ERR_SCRATCH = -10   /* kp_tucker_noalloc: the intermediates need more than
+                            KP_NOALLOC_SCRATCH_BYTES */
 } kp_status;
 
 typedef enum { KP_F64 = 0, KP_F32 = 1 } kp_dtype;
@@ -157,6 +159,28 @@ size_t kp_tucker_cache_size(const kp_tensor* T, const kp_matrix* const* L);
 int kp_tucker(const kp_tensor* T, const kp_matrix* const* L, kp_tensor* S,
               int prec, void* ws, size_t ws_bytes,
               void* cache, size_t cache_bytes, hipStream_t stream);
+
+/* ---- Tucker operator without caller memory ------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the same result
+ * as kp_tucker without a cache, with the intermediates held in a buffer the
+ * library owns instead of a caller workspace. The buffer is a fixed device
+ * array of KP_NOALLOC_SCRATCH_BYTES per device, kept from the first call on
+ * that device until the process ends; the first call on a device looks up
+ * its address (hipGetSymbolAddress), later calls do no set-up at all. The
+ * call itself allocates and frees nothing; it only enqueues the products on
+ * `stream`.
+ * Every call on one device shares that device's buffer: calls whose work
+ * overlaps in time on one device (different streams, or host threads without
+ * ordering) race on it and must be serialised by the caller. Nothing in the
+ * buffer needs to start at zero; it keeps the last call's intermediates.
+ * Errors: as kp_tucker (argument errors before anything is enqueued);
+ * KP_ERR_SCRATCH if kp_tucker_workspace(T, L, prec) exceeds
+ * KP_NOALLOC_SCRATCH_BYTES; KP_ERR_HIP if the address look-up fails. */
+#define KP_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20) /* 128 MiB */
+size_t kp_noalloc_scratch_bytes(void);
+int kp_tucker_noalloc(const kp_tensor* T, const kp_matrix* const* L, kp_tensor* S, int prec,
+                      hipStream_t stream);
 
 /* ---- complex Tucker operator (Sec. 2 over C; Sec. 3 conjugate-transpose form) -
  * A complex tensor is stored as interleaved (real, imaginary) pairs: T is a

@@ -7,9 +7,11 @@ thin torch binding (ops) that only marshals arguments.
 """
 from .ops import (mump, tucker, tucker_with_cache, tucker_backward,  # noqa: F401
                   tucker_autograd, TuckerFunction, expm, BatchedTucker, force_tile, kronsum,
-                  tridiag_inverse, pcg_kronsum, semilinear_imex, tucker_complex)
+                  tridiag_inverse, pcg_kronsum, semilinear_imex, tucker_complex,
+                  tucker_noalloc)
 from . import tune  # noqa: F401,E402
 
 __all__ = ["mump", "tucker", "tucker_with_cache", "tucker_backward", "tucker_autograd",
            "TuckerFunction", "expm", "BatchedTucker", "force_tile", "kronsum",
-           "tridiag_inverse", "pcg_kronsum", "semilinear_imex", "tucker_complex", "tune"]
+           "tridiag_inverse", "pcg_kronsum", "semilinear_imex", "tucker_complex",
+           "tucker_noalloc", "tune"]

@@ -23,7 +23,7 @@ KP_OPT_FUSE = 1
 STATUS = {
     0: "KP_OK", -1: "KP_ERR_NULL", -2: "KP_ERR_ORDER", -3: "KP_ERR_MODE",
     -4: "KP_ERR_SHAPE", -5: "KP_ERR_DTYPE", -6: "KP_ERR_ALIAS",
-    -7: "KP_ERR_WORKSPACE", -8: "KP_ERR_HIP", -9: "KP_ERR_VALUE",
+    -7: "KP_ERR_WORKSPACE", -8: "KP_ERR_HIP", -9: "KP_ERR_VALUE", -10: "KP_ERR_SCRATCH",
 }
 
 
@@ -74,6 +74,8 @@ SIGNATURES = {
     "kp_tucker_cache_size": (_S, [_T, _MA]),
     "kp_tucker_order": (ctypes.c_int, [_T, _MA, P(ctypes.c_int), P(ctypes.c_int)]),
     "kp_tucker": (ctypes.c_int, [_T, _MA, _T, ctypes.c_int, _V, _S, _V, _S, _V]),
+    "kp_noalloc_scratch_bytes": (_S, []),
+    "kp_tucker_noalloc": (ctypes.c_int, [_T, _MA, _T, ctypes.c_int, _V]),
     "kp_tucker_complex_workspace": (_S, [_T, _MA, _MA, ctypes.c_int, ctypes.c_int]),
     "kp_tucker_complex": (ctypes.c_int, [_T, _MA, _MA, _T, ctypes.c_int, ctypes.c_int, _V, _S,
                                          _V]),

@@ -297,6 +297,7 @@ const char* kp_strerror(int status) {
     case KP_ERR_WORKSPACE: return "workspace missing or too small";
     case KP_ERR_HIP: return "HIP launch failed";
     case KP_ERR_VALUE: return "scalar argument out of range";
+    case KP_ERR_SCRATCH: return "intermediates exceed the library's fixed scratch buffer";
     default: return "unknown status";
   }
 }

@@ -172,6 +172,28 @@ def tucker(T, Ls, prec="native"):
     return _tucker_call(T, Ls, prec, False)[0]
 
 
+def tucker_noalloc(T, Ls, prec="native", out=None):
+    """S = T x_1 L_1 x_2 ... x_d L_d with the intermediates in the library's
+    fixed device buffer (kp_tucker_noalloc): no workspace is allocated, and
+    with ``out`` given (contiguous, S's shape and dtype) nothing at all.
+    Calls that overlap in time on one device race on that buffer."""
+    _check_device(T, *Ls)
+    d = T.dim()
+    if len(Ls) != d:
+        raise ValueError(f"need {d} factors, got {len(Ls)}")
+    Tc = _canon(T)
+    shape = [T.shape[k] if Ls[k] is None else Ls[k].shape[0] for k in range(d)]
+    if out is None:
+        out = torch.empty(shape, dtype=T.dtype, device=T.device)
+    elif list(out.shape) != shape or out.dtype != T.dtype or not out.is_contiguous():
+        raise ValueError("output must be a contiguous tensor of S's shape and T's dtype")
+    mds = [None if L is None else _mdesc(L) for L in Ls][::-1]
+    td, sd = _tdesc(Tc, True), _tdesc(out, True)
+    check(lib().kp_tucker_noalloc(ctypes.byref(td), _mlist(mds), ctypes.byref(sd), _prec(prec),
+                                  _stream()), "kp_tucker_noalloc")
+    return out
+
+
 def tucker_backward(G, T, Ls, prec="native", cache=None, need_dT=True, need_dL=None):
     """Gradient of <G, tucker(T, Ls)>: returns (dT, [dL_1, ..., dL_d]).
 

@@ -124,6 +124,28 @@ def mlist(L, ms):
 
 
 @no_device
+def test_tucker_noalloc_argument_errors(lib, L):
+    """The allocation-free Tucker call rejects, before touching a device,
+    argument errors (as kp_tucker) and problems whose intermediates exceed
+    the fixed scratch buffer."""
+    assert lib.kp_noalloc_scratch_bytes() == 128 << 20
+    T = tensor(L, [4, 5, 6], dtype=1)
+    S = tensor(L, [3, 2, 5], dtype=1, data=FAKE + 0x300000)
+    arr = mlist(L, [matrix(L, 3, 4, 1), matrix(L, 2, 5, 1), matrix(L, 5, 6, 1)])
+    bad = mlist(L, [matrix(L, 3, 4, 1), matrix(L, 2, 6, 1), matrix(L, 5, 6, 1)])
+    assert lib.kp_tucker_noalloc(ctypes.byref(T), bad, ctypes.byref(S), 0, None) == -4
+    assert lib.kp_tucker_noalloc(None, arr, ctypes.byref(S), 0, None) == -1
+    # FP64 512^3 -> 512^3: two 1 GiB intermediates, far past 128 MiB
+    Tb = tensor(L, [512, 512, 512])
+    Sb = tensor(L, [512, 512, 512], data=FAKE + (1 << 34))
+    big = mlist(L, [matrix(L, 512, 512, data=FAKE + (1 << 33) + 0x100000 * j) for j in range(3)])
+    need = lib.kp_tucker_workspace(ctypes.byref(Tb), big, 0)
+    assert need > lib.kp_noalloc_scratch_bytes()
+    assert lib.kp_tucker_noalloc(ctypes.byref(Tb), big, ctypes.byref(Sb), 0, None) == -10
+    assert lib.kp_strerror(-10) != b"unknown status"
+
+
+@no_device
 def test_mump_argument_errors(lib, L):
     T = tensor(L, [4, 5, 6])
     S = tensor(L, [4, 7, 6], data=FAKE + 0x200000)
