@@ -121,11 +121,15 @@ SIGNATURES = {
 _lib = None
 
 
-def load(path=LIB_PATH):
-    """Open libkp.so and declare its prototypes. Raises if it is missing."""
+def load(path=None):
+    """Open libkp.so and declare its prototypes. Raises if it is missing.
+    KP_LIBRARY in the environment names another build of the same library
+    (the host-sanitizer build used by the host-side tests)."""
     global _lib
     if _lib is not None:
         return _lib
+    if path is None:
+        path = os.environ.get("KP_LIBRARY") or LIB_PATH
     if not os.path.exists(path):
         raise ImportError(
             f"{path} is missing: build it with `python -m paper_2112_11238_amd.build` "
