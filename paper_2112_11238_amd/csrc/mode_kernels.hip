@@ -112,7 +112,7 @@ const Variant* find_variant(int form, const ModeTile& t) {
 // Default tiles, chosen from tile sweeps on cubes with n = 128..324 (cube200
 // among them) and small modes: FP64 favours 7 (or, at 112 < n <= 184, 4)
 // blocks along n with 8-wide k chunks (small LDS and register footprint),
-// with two chunks of loads in flight once m >= 256; FP32 7 blocks (8 at
+// with two chunks of loads in flight once m >= 160; FP32 7 blocks (8 at
 // n <= 128, 4 at 128 < n <= 184) with two chunks of loads in flight; the
 // BF16 split forms 4 blocks (BF16x6 with two chunks in flight). Short
 // contractions (m <= 64; FP64: m <= 32, or m <= 64 on the lead layout)
@@ -147,7 +147,7 @@ ModeTile pick_tile(int form, int64_t Il, int64_t m, int64_t n, int64_t Ir) {
       t.fb = 1;
       t.nb = (n <= 64 || (n > 112 && n <= 184)) ? 4 : 7;
       // long contractions keep two chunks of loads in flight
-      if (t.nb == 7 && m >= 256) {
+      if (t.nb == 7 && m >= 160) {
         t.occ = 2;
         t.pf = 2;
       }

@@ -77,14 +77,18 @@ __device__ __forceinline__ void store_out(G y, __amdgpu_buffer_rsrc_t rs, uint32
 // gfx9 family; loads at offsets at or past the resource's size return zero.
 constexpr int kBufferFlags = 0x00020000;
 
+// off: per-lane byte offset; soff: a wave-uniform byte offset added to it.
 template <typename G>
-__device__ __forceinline__ G buffer_load(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
+__device__ __forceinline__ G buffer_load(__amdgpu_buffer_rsrc_t rs, uint32_t off,
+                                         uint32_t soff = 0) {
   if constexpr (sizeof(G) == 8) {
     typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-    const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(rs, static_cast<int>(off), 0, 0);
+    const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(rs, static_cast<int>(off),
+                                                         static_cast<int>(soff), 0);
     return __builtin_bit_cast(G, v);
   } else {
-    const unsigned int v = __builtin_amdgcn_raw_buffer_load_b32(rs, static_cast<int>(off), 0, 0);
+    const unsigned int v = __builtin_amdgcn_raw_buffer_load_b32(rs, static_cast<int>(off),
+                                                                static_cast<int>(soff), 0);
     return __builtin_bit_cast(G, v);
   }
 }
@@ -187,6 +191,52 @@ __device__ __forceinline__ void macro_step(const Frag<FORM> (&A)[FormT<FORM>::P]
   }
 }
 
+// One macro step for an R x C grid of output blocks at once: A[r] feeds
+// block row r, B[c] block column c. The products are issued slot by slot
+// across all blocks (slot = one of the per-block MFMAs of macro_step, in the
+// same order), so consecutive MFMAs never write the same accumulator and
+// each accumulator still receives its products in macro_step's order (the
+// results are bitwise those of R x C separate macro steps).
+template <int FORM, int R, int C>
+__device__ __forceinline__ void macro_step_grid(
+    const Frag<FORM> (&A)[R][FormT<FORM>::P], const Frag<FORM> (&B)[C][FormT<FORM>::P],
+    typename FormT<FORM>::acc_t (&hi)[R][C], typename FormT<FORM>::acc_t (&lo)[R][C]) {
+  auto each = [&](auto&& f) {
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int c = 0; c < C; ++c) f(r, c);
+  };
+  if constexpr (FORM == FORM_F64) {
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+      each([&](int r, int c) {
+        hi[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[r][0][s], B[c][0][s], hi[r][c], 0, 0, 0);
+      });
+  } else if constexpr (FORM == FORM_F32) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+      each([&](int r, int c) {
+        hi[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[r][0][s], B[c][0][s], hi[r][c], 0, 0, 0);
+      });
+  } else {
+    // correction products (smallest first) into lo, the leading one into hi
+    auto slot = [&](int pa, int pb, auto& acc) {
+      each([&](int r, int c) {
+        acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[r][pa], B[c][pb], acc[r][c], 0, 0, 0);
+      });
+    };
+    if constexpr (FORM == FORM_BF16X6) {
+      slot(0, 2, lo);
+      slot(1, 1, lo);
+      slot(2, 0, lo);
+    }
+    slot(0, 1, lo);
+    slot(1, 0, lo);
+    slot(0, 0, hi);
+  }
+}
+
 // NB: 16-blocks along n per workgroup (every wave covers all of them).
 // FB: 16-blocks of fibers per wave; 4 waves split the fibers, so a workgroup
 //     covers 64*FB fibers.
@@ -257,7 +307,10 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t bx, int64_t
   // host splits launches so that each stays below 2^31 bytes). Rows past
   // the end are clamped to the last row: they only feed accumulator rows
   // or columns that are never stored. Only the k tail needs zeros.
-  uint32_t xo[XT][KV], lo_[LT][KV];
+  // Offsets of each task's first element; element e of the group sits e
+  // element strides further (X: Il or 1 elements, L: cs elements), a
+  // uniform step passed as the loads' scalar offset.
+  uint32_t xo[XT], lo_[LT];
   int xkg[XT], lkg[LT];
   // 32-bit index math: every element offset of X, Y and the span of L are
   // below 2^31 bytes (the host splits launches and checks factor spans)
@@ -282,10 +335,7 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t bx, int64_t
       rowoff = f * m32;
     }
     xkg[s] = kg;
-#pragma unroll
-    for (int e = 0; e < KV; ++e)
-      xo[s][e] = (rowoff + static_cast<uint32_t>(kg * KV + e) * xkstep) *
-                 static_cast<uint32_t>(sizeof(G));
+    xo[s] = (rowoff + static_cast<uint32_t>(kg * KV) * xkstep) * static_cast<uint32_t>(sizeof(G));
   }
   const uint32_t rs32 = static_cast<uint32_t>(a.rs), cs32 = static_cast<uint32_t>(a.cs);
 #pragma unroll
@@ -297,10 +347,7 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t bx, int64_t
     lkg[s] = kg;
     // offsets of k past m (tail chunk only) may wrap; they are replaced by
     // an out-of-range offset before use
-#pragma unroll
-    for (int e = 0; e < KV; ++e)
-      lo_[s][e] = (i * rs32 + static_cast<uint32_t>(kg * KV + e) * cs32) *
-                  static_cast<uint32_t>(sizeof(G));
+    lo_[s] = (i * rs32 + static_cast<uint32_t>(kg * KV) * cs32) * static_cast<uint32_t>(sizeof(G));
   }
   static_assert(PF == 1 || PF == 2, "prefetch distance 1 or 2");
   G xr[PF][XT][KV], lr[PF][LT][KV];
@@ -316,6 +363,9 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t bx, int64_t
   const uint32_t x_bytes = static_cast<uint32_t>(a.Il * a.m * a.Ir * sizeof(G));
   const uint32_t l_bytes =
       static_cast<uint32_t>(((n - 1) * a.rs + (m - 1) * a.cs + 1) * sizeof(G));
+  // byte steps between the KV elements of one task's group
+  const uint32_t xes = xkstep * static_cast<uint32_t>(sizeof(G));
+  const uint32_t les = cs32 * static_cast<uint32_t>(sizeof(G));
   auto load_chunk = [&](int64_t k0, auto check, auto set) {
     constexpr bool CHECK = decltype(check)::value;
     constexpr int SET = decltype(set)::value;
@@ -348,26 +398,32 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t bx, int64_t
 #pragma unroll
     for (int s = 0; s < XT; ++s) {
       if constexpr (VEC && !INNER) {
-        load_group(xrs, xo[s][0], k0 + xkg[s] * KV, xr[SET][s]);
+        load_group(xrs, xo[s], k0 + xkg[s] * KV, xr[SET][s]);
       } else {
 #pragma unroll
         for (int e = 0; e < KV; ++e) {
-          uint32_t off = xo[s][e];
-          if constexpr (CHECK) off = k0 + xkg[s] * KV + e < m ? off : kOut;
-          xr[SET][s][e] = buffer_load<G>(xrs, off);
+          if constexpr (CHECK) {
+            const uint32_t off = k0 + xkg[s] * KV + e < m ? xo[s] + e * xes : kOut;
+            xr[SET][s][e] = buffer_load<G>(xrs, off);
+          } else {
+            xr[SET][s][e] = buffer_load<G>(xrs, xo[s], e * xes);
+          }
         }
       }
     }
 #pragma unroll
     for (int s = 0; s < LT; ++s) {
       if constexpr (VEC) {
-        load_group(lrs, lo_[s][0], k0 + lkg[s] * KV, lr[SET][s]);
+        load_group(lrs, lo_[s], k0 + lkg[s] * KV, lr[SET][s]);
       } else {
 #pragma unroll
         for (int e = 0; e < KV; ++e) {
-          uint32_t off = lo_[s][e];
-          if constexpr (CHECK) off = k0 + lkg[s] * KV + e < m ? off : kOut;
-          lr[SET][s][e] = buffer_load<G>(lrs, off);
+          if constexpr (CHECK) {
+            const uint32_t off = k0 + lkg[s] * KV + e < m ? lo_[s] + e * les : kOut;
+            lr[SET][s][e] = buffer_load<G>(lrs, off);
+          } else {
+            lr[SET][s][e] = buffer_load<G>(lrs, lo_[s], e * les);
+          }
         }
       }
     }
@@ -428,12 +484,22 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t bx, int64_t
     else
       load_chunk(ch * BK, Checked{}, set);
   };
-  // n blocks of this tile that hold rows below n (the rest are skipped)
+  // n blocks of this tile that hold rows below n. A tile computes either all
+  // NB blocks or, when at most the first NH hold rows below n (the last n
+  // tile), only those NH; the blocks past them hold no output row. NH is
+  // NB - 1 for tall tiles (n = 200 with 7-block tiles: 7 + 6 blocks), else
+  // half of NB.
   const int nbu = static_cast<int>((n - i0 + 15) / 16);
-  auto compute = [&](int buf) {
+  constexpr int NH = NB >= 5 ? NB - 1 : (NB + 1) / 2;
+  // One chunk's macro steps over the first NBC n blocks: every fragment of a
+  // macro step is read from LDS first, then its MFMAs are issued across all
+  // blocks (macro_step_grid).
+  auto compute_n = [&](int buf, auto nbc) {
+    constexpr int NBC = decltype(nbc)::value;
 #pragma unroll
     for (int kk = 0; kk < BK; kk += MK) {
       FragT xa[FB][P];
+      FragT la[NBC][P];
 #pragma unroll
       for (int fb = 0; fb < FB; ++fb)
 #pragma unroll
@@ -441,23 +507,55 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t bx, int64_t
           xa[fb][p] = *reinterpret_cast<const FragT*>(
               &sX[buf][p][w * 16 * FB + fb * 16 + c][kk + KV * g]);
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-        if (nb >= nbu) break;
-        FragT la[P];
+      for (int nb = 0; nb < NBC; ++nb)
 #pragma unroll
         for (int p = 0; p < P; ++p)
-          la[p] = *reinterpret_cast<const FragT*>(&sL[buf][p][nb * 16 + c][kk + KV * g]);
+          la[nb][p] = *reinterpret_cast<const FragT*>(&sL[buf][p][nb * 16 + c][kk + KV * g]);
+      // A operand = MFMA rows, B = MFMA (memory-contiguous) columns; the
+      // accumulators of the first NBC blocks are passed as a grid of their own
+      if constexpr (INNER) {
+        typename FT::acc_t h[NBC][FB], l[NBC][FB];
 #pragma unroll
-        for (int fb = 0; fb < FB; ++fb) {
-          // A operand = MFMA rows, B = MFMA (memory-contiguous) columns
-          if constexpr (INNER)
-            macro_step<FORM>(la, xa[fb], hi[nb][fb], lo[nb][fb]);
-          else
-            macro_step<FORM>(xa[fb], la, hi[fb][nb], lo[fb][nb]);
-        }
+        for (int nb = 0; nb < NBC; ++nb)
+#pragma unroll
+          for (int fb = 0; fb < FB; ++fb) {
+            h[nb][fb] = hi[nb][fb];
+            l[nb][fb] = lo[nb][fb];
+          }
+        macro_step_grid<FORM, NBC, FB>(la, xa, h, l);
+#pragma unroll
+        for (int nb = 0; nb < NBC; ++nb)
+#pragma unroll
+          for (int fb = 0; fb < FB; ++fb) {
+            hi[nb][fb] = h[nb][fb];
+            lo[nb][fb] = l[nb][fb];
+          }
+      } else {
+        // hi[fb][nb] with NB columns: the first NBC of each row
+        typename FT::acc_t h[FB][NBC], l[FB][NBC];
+#pragma unroll
+        for (int fb = 0; fb < FB; ++fb)
+#pragma unroll
+          for (int nb = 0; nb < NBC; ++nb) {
+            h[fb][nb] = hi[fb][nb];
+            l[fb][nb] = lo[fb][nb];
+          }
+        macro_step_grid<FORM, FB, NBC>(xa, la, h, l);
+#pragma unroll
+        for (int fb = 0; fb < FB; ++fb)
+#pragma unroll
+          for (int nb = 0; nb < NBC; ++nb) {
+            hi[fb][nb] = h[fb][nb];
+            lo[fb][nb] = l[fb][nb];
+          }
       }
     }
   };
+  // The whole k loop for tiles computing the first NBC n blocks (NBC = NB,
+  // or NH for a last n tile with at most NH blocks below n): the two loops
+  // are separate code, so each keeps its own register allocation.
+  auto kloop = [&](auto nbc) {
+  auto compute = [&](int buf) { compute_n(buf, nbc); };
   if constexpr (PF == 1) {
     if (nchunks > 0) {
       load(0, Set0{});
@@ -508,6 +606,11 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t bx, int64_t
       __syncthreads();
     }
   }
+  };
+  if (NH < NB && nbu <= NH)
+    kloop(std::integral_constant<int, NH>{});
+  else
+    kloop(std::integral_constant<int, NB>{});
 
   // Store: MFMA column = lane & 15 is the memory-contiguous output index.
   // Through a buffer resource over Y: rows past n and fibers past F get an

@@ -195,33 +195,32 @@ __device__ __forceinline__ void pair_run(const PairArgs& a, int64_t t0, int64_t 
     if (nx < ntiles) load_x(nx);
     // stage 1: Z[i1][f][j2] for the j2 of this wave (w, w + 4, ...)
     for (int j2 = w; j2 < KP2; j2 += 4) {
-      acc_t hi[NB1], lo[NB1];
+      acc_t hi[NB1][1], lo[NB1][1];
 #pragma unroll
       for (int q = 0; q < NB1; ++q) {
-        hi[q] = acc_t{};
-        lo[q] = acc_t{};
+        hi[q][0] = acc_t{};
+        lo[q][0] = acc_t{};
       }
 #pragma unroll
       for (int kk = 0; kk < KP1; kk += MK) {
-        FragT xb[P];
+        FragT xb[1][P];
+        FragT la[NB1][P];
 #pragma unroll
         for (int p = 0; p < P; ++p)
-          xb[p] = *reinterpret_cast<const FragT*>(&sX[p][j2][c][kk + KV * g]);
+          xb[0][p] = *reinterpret_cast<const FragT*>(&sX[p][j2][c][kk + KV * g]);
 #pragma unroll
-        for (int q = 0; q < NB1; ++q) {
-          FragT la[P];
+        for (int q = 0; q < NB1; ++q)
 #pragma unroll
           for (int p = 0; p < P; ++p)
-            la[p] = *reinterpret_cast<const FragT*>(&sL1[p][q * 16 + c][kk + KV * g]);
-          macro_step<FORM>(la, xb, hi[q], lo[q]);
-        }
+            la[q][p] = *reinterpret_cast<const FragT*>(&sL1[p][q * 16 + c][kk + KV * g]);
+        macro_step_grid<FORM, NB1, 1>(la, xb, hi, lo);
       }
       // rows i1 = q*16 + row(lane, v), column f = c; Z rounded to G, split
       // into the planes when the form has them
 #pragma unroll
       for (int q = 0; q < NB1; ++q) {
-        acc_t val = hi[q];
-        if constexpr (SPLIT) val = hi[q] + lo[q];
+        acc_t val = hi[q][0];
+        if constexpr (SPLIT) val = hi[q][0] + lo[q][0];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int i1 = q * 16 + FT::row(lane, v);
@@ -245,31 +244,30 @@ __device__ __forceinline__ void pair_run(const PairArgs& a, int64_t t0, int64_t 
     const uint32_t rb = r / Il;
     const uint32_t ybase = (r - rb * Il) + Il * n1 * n2 * rb;
     for (int i1 = w; i1 < static_cast<int>(n1); i1 += 4) {
-      acc_t hi[NB2], lo[NB2];
+      acc_t hi[NB2][1], lo[NB2][1];
 #pragma unroll
       for (int q = 0; q < NB2; ++q) {
-        hi[q] = acc_t{};
-        lo[q] = acc_t{};
+        hi[q][0] = acc_t{};
+        lo[q][0] = acc_t{};
       }
 #pragma unroll
       for (int kk = 0; kk < KP2; kk += MK) {
-        FragT zb[P];
+        FragT zb[1][P];
+        FragT la[NB2][P];
 #pragma unroll
         for (int p = 0; p < P; ++p)
-          zb[p] = *reinterpret_cast<const FragT*>(&sZ[p][i1][c][kk + KV * g]);
+          zb[0][p] = *reinterpret_cast<const FragT*>(&sZ[p][i1][c][kk + KV * g]);
 #pragma unroll
-        for (int q = 0; q < NB2; ++q) {
-          FragT la[P];
+        for (int q = 0; q < NB2; ++q)
 #pragma unroll
           for (int p = 0; p < P; ++p)
-            la[p] = *reinterpret_cast<const FragT*>(&sL2[p][q * 16 + c][kk + KV * g]);
-          macro_step<FORM>(la, zb, hi[q], lo[q]);
-        }
+            la[q][p] = *reinterpret_cast<const FragT*>(&sL2[p][q * 16 + c][kk + KV * g]);
+        macro_step_grid<FORM, NB2, 1>(la, zb, hi, lo);
       }
 #pragma unroll
       for (int q = 0; q < NB2; ++q) {
-        acc_t val = hi[q];
-        if constexpr (SPLIT) val = hi[q] + lo[q];
+        acc_t val = hi[q][0];
+        if constexpr (SPLIT) val = hi[q][0] + lo[q][0];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const uint32_t i2 = q * 16 + FT::row(lane, v);

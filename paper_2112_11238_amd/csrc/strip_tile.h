@@ -203,20 +203,17 @@ __device__ __forceinline__ void strip_run(const ModeArgs& a, int64_t by, int64_t
         for (int p = 0; p < P; ++p)
           xa[fb][p] = *reinterpret_cast<const FragT*>(
               &sX[buf][p][w * 16 * FB + fb * 16 + c][kk + KV * g]);
+      FragT la[NB][P];
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-        FragT la[P];
+      for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
         for (int p = 0; p < P; ++p)
-          la[p] = *reinterpret_cast<const FragT*>(&sL[p][nb * 16 + c][kk + KV * g]);
-#pragma unroll
-        for (int fb = 0; fb < FB; ++fb) {
-          if constexpr (INNER)
-            macro_step<FORM>(la, xa[fb], hi[nb][fb], lo[nb][fb]);
-          else
-            macro_step<FORM>(xa[fb], la, hi[fb][nb], lo[fb][nb]);
-        }
-      }
+          la[nb][p] = *reinterpret_cast<const FragT*>(&sL[p][nb * 16 + c][kk + KV * g]);
+      // products issued slot by slot across the blocks (macro_step_grid)
+      if constexpr (INNER)
+        macro_step_grid<FORM, NB, FB>(la, xa, hi, lo);
+      else
+        macro_step_grid<FORM, FB, NB>(xa, la, hi, lo);
     }
     // outputs of this tile (MFMA column = memory-contiguous index), through a
     // buffer resource over Y: rows past n and fibers past F get an offset
