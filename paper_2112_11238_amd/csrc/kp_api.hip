@@ -212,6 +212,40 @@ bool fuse_step(const ChainPlan& p, int s, int d, const kp_matrix* const* L, int 
   return true;
 }
 
+// Which steps of a chain without a cache start a fused pass (fused[s]: steps
+// s and s + 1 in one launch). Among the eligible pairs (fuse_step), the
+// non-overlapping set that moves the fewest tensor elements through HBM: an
+// unfused step reads its input and writes its output, a fused pair skips the
+// intermediate between its two steps. Ties keep the plan with more fused
+// passes, then the earlier ones.
+void plan_fusion(const ChainPlan& p, int d, const kp_matrix* const* L, int form, bool* fused) {
+  int64_t best[KP_MAX_ORDER + 2];
+  bool pick[KP_MAX_ORDER + 1];
+  best[p.count] = 0;
+  best[p.count + 1] = 0;
+  for (int s = p.count - 1; s >= 0; --s) {
+    fused[s] = false;
+    pick[s] = false;
+    best[s] = p.size[s] + p.size[s + 1] + best[s + 1];
+    tile::PairArgs pa;
+    if (s + 1 < p.count && fuse_step(p, s, d, L, form, &pa)) {
+      const int64_t c = p.size[s] + p.size[s + 2] + best[s + 2];
+      if (c <= best[s]) {
+        best[s] = c;
+        pick[s] = true;
+      }
+    }
+  }
+  for (int s = 0; s < p.count;) {
+    if (pick[s]) {
+      fused[s] = true;
+      s += 2;
+    } else {
+      ++s;
+    }
+  }
+}
+
 int validate_tucker_args(const kp_tensor* T, const kp_matrix* const* L, int prec) {
   int st = check_tensor(T, true);
   if (st) return st;
@@ -448,12 +482,14 @@ int kp_tucker(const kp_tensor* T, const kp_matrix* const* L, kp_tensor* S, int p
     cur = cur == 0 ? 1 : 0;
     return static_cast<char*>(ws) + (cur ? off1 : 0);
   };
+  // steps s and s + 1 on modes k and k + 1 run as one fused pass where the
+  // fusion plan says so (never with a cache, which must hold every partial)
+  bool fused[KP_MAX_ORDER] = {};
+  if (!cache) plan_fusion(p, T->d, L, form, fused);
   for (int s = 0; s < p.count; ++s) {
     const int k = p.order[s];
-    // steps s and s + 1 on modes k and k + 1: one fused pass when possible
-    // (never with a cache, which must hold every partial product)
     tile::PairArgs pa;
-    if (!cache && fuse_step(p, s, T->d, L, form, &pa)) {
+    if (fused[s] && fuse_step(p, s, T->d, L, form, &pa)) {
       pa.X = src;
       pa.Y = dst_of(s + 1);
       st = hip_status(launch_pair(form, pa, stream));
@@ -656,11 +692,13 @@ int kp_tucker_products(const kp_tensor* T, const kp_matrix* const* L, int prec, 
   if (which < 2 || which == 3) {
     ChainPlan p;
     make_chain(*T, L, which == 1, &p);
+    bool fused[KP_MAX_ORDER] = {};
+    if (which == 3) plan_fusion(p, d, L, form, fused);
     for (int s = 0; s < p.count; ++s) {
       const int k = p.order[s];
       const ModeArgs a = mode_args(nullptr, nullptr, p.dims[s], d, k, *L[k], 0);
       tile::PairArgs pa;
-      if (which == 3 && fuse_step(p, s, d, L, form, &pa)) {
+      if (fused[s] && fuse_step(p, s, d, L, form, &pa)) {
         if (count < cap) {
           kp_tune_entry& e = out[count];
           memset(&e, 0, sizeof(e));
