@@ -412,8 +412,12 @@ typedef struct {
  * match, which is what is stored), or a strip tile is shorter than m. */
 int kp_tune_set(const kp_tune_entry* e);
 /* The tile a product with this key gets when no tile is forced: returns 1
- * and fills *out from the table if the key is tuned, 0 and fills *out with
- * the built-in default otherwise; KP_ERR_NULL / KP_ERR_VALUE on bad input. */
+ * and fills *out (with the queried key) from the table if the key, or its
+ * shape class, is tuned, 0 and fills *out with the built-in default
+ * otherwise; KP_ERR_NULL / KP_ERR_VALUE on bad input. Shape class: a key
+ * without an entry of its own takes the entry with the same form, layout
+ * (Il = 1 or Il > 1), m and n whose fiber count Il*Ir is nearest in ratio
+ * to its own, within a factor of two (ties: the smaller count). */
 int kp_tune_lookup(int form, int64_t Il, int64_t m, int64_t n, int64_t Ir, kp_tune_entry* out);
 /* Number of entries; kp_tune_list copies the first min(cap, count) entries
  * (in key order) to out (may be NULL when cap is 0) and returns the count. */

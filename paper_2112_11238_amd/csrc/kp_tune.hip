@@ -1,6 +1,7 @@
 // Tile selection: a process-wide forced tile (tests cover every compiled
 // variant with it; the tuning driver times candidates with it) and the tile
-// table, keyed by the exact product shape, that the tuning driver fills.
+// table, keyed by the exact product shape, that the tuning driver fills; a
+// view without an entry of its own takes the entry of its shape class.
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -52,13 +53,37 @@ bool g_fuse = true;
 
 bool fusion_enabled() { return g_fuse; }
 
+// Exact view first; otherwise the entry of the same shape class: same form,
+// same layout (I_l = 1 or I_l > 1), same m and n, and a fiber count within
+// a factor of two (the nearest in ratio; ties: the smaller count). A tile
+// tuned on one size of a product thus also serves its neighbours.
 bool tuned_tile(int form, int64_t Il, int64_t m, int64_t n, int64_t Ir, ModeTile* out) {
   std::lock_guard<std::mutex> lock(g_mu);
   const auto& t = table();
   if (t.empty()) return false;
   const auto it = t.find(Key{form, Il, m, n, Ir});
-  if (it == t.end()) return false;
-  *out = it->second;
+  if (it != t.end()) {
+    *out = it->second;
+    return true;
+  }
+  const bool lead = Il == 1;
+  const double F = static_cast<double>(Il) * static_cast<double>(Ir);
+  const ModeTile* best = nullptr;
+  double best_ratio = 2.0 + 1e-9, best_F = 0.0;
+  for (const auto& kv : t) {
+    const Key& k = kv.first;
+    if (std::get<0>(k) != form || std::get<2>(k) != m || std::get<3>(k) != n) continue;
+    if ((std::get<1>(k) == 1) != lead) continue;
+    const double Fk = static_cast<double>(std::get<1>(k)) * static_cast<double>(std::get<4>(k));
+    const double ratio = Fk > F ? Fk / F : F / Fk;
+    if (ratio < best_ratio || (ratio == best_ratio && Fk < best_F)) {
+      best_ratio = ratio;
+      best_F = Fk;
+      best = &kv.second;
+    }
+  }
+  if (!best) return false;
+  *out = *best;
   return true;
 }
 

@@ -2,11 +2,13 @@
 
 Each mu-mode product takes its tile from the library's tile table, keyed by
 the arithmetic form and the product's exact 3-index view (I_l, m, n, I_r),
-before the built-in defaults (include/kp.h, kp_tune_*). This module fills
-that table: it asks the library which products a call launches
-(kp_tucker_products), times every compiled tile variant on each of them with
-HIP events, and records the fastest. Tables can be saved to and loaded from
-JSON.
+or failing that by its shape class (same form, layout, m and n, fiber count
+within a factor of two), before the built-in defaults (include/kp.h,
+kp_tune_*). This module fills that table: it asks the library which products
+a call launches (kp_tucker_products), times every compiled tile variant on
+each of them with HIP events, and records the fastest. Tables are saved to
+and loaded from JSON together with the device architecture, library version
+and compiled-tile signature they were tuned for; loading checks them.
 
 Two timing objectives:
 
@@ -95,15 +97,50 @@ def lookup(form, Il, m, n, Ir):
     return bool(st), (e.nb, e.fb, e.bk, e.occ, e.pf, e.kind)
 
 
+def device_arch():
+    """Architecture name of the current device (e.g. 'gfx950'), or None."""
+    try:
+        if torch.cuda.is_available():
+            return torch.cuda.get_device_properties(torch.cuda.current_device()).gcnArchName.split(
+                ":")[0]
+    except Exception:  # pragma: no cover
+        pass
+    return None
+
+
+def variants_signature():
+    """Digest of every compiled tile (standalone and batched, every form): a
+    saved table is only meaningful for the library build it was tuned on."""
+    import hashlib
+    h = hashlib.sha256()
+    for form in sorted(FORMS.values()):
+        for batch in (False, True):
+            h.update(repr((form, batch, variants(form, batch=batch))).encode())
+    return h.hexdigest()[:16]
+
+
 def save(path):
+    """Write the table with what it was tuned for: the device architecture,
+    the library version and the compiled-tile signature."""
     with open(path, "w") as fh:
-        json.dump({"kp_version": lib().kp_version(), "entries": entries()}, fh, indent=1)
+        json.dump({"kp_version": lib().kp_version(), "arch": device_arch(),
+                   "variants": variants_signature(), "entries": entries()}, fh, indent=1)
 
 
-def load(path):
-    """Add the entries of a saved table; returns how many were loaded."""
+def load(path, force=False):
+    """Add the entries of a saved table; returns how many were loaded.
+    Refuses (ValueError) a table tuned for another library version, another
+    device architecture or other compiled tiles, unless ``force``."""
     with open(path) as fh:
         rec = json.load(fh)
+    if not force:
+        if rec.get("kp_version") != lib().kp_version():
+            raise ValueError(f"table tuned for library version {rec.get('kp_version')}")
+        arch = device_arch()
+        if rec.get("arch") is not None and arch is not None and rec["arch"] != arch:
+            raise ValueError(f"table tuned on {rec['arch']}, this device is {arch}")
+        if rec.get("variants") is not None and rec["variants"] != variants_signature():
+            raise ValueError("table tuned for a library build with other compiled tiles")
     for e in rec["entries"]:
         set_tile(e["form"], e["Il"], e["m"], e["n"], e["Ir"],
                  (e["nb"], e["fb"], e["bk"], e["occ"], e["pf"], e.get("kind", 0)))

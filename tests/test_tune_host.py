@@ -122,7 +122,21 @@ def test_set_lookup_list_clear(lib, L, tune):
     tune.set_tile("f64", 40, 200, 200, 200, (7, 1, 8, 2, 2))     # replace
     assert tune.lookup("f64", 40, 200, 200, 200) == (True, (7, 1, 8, 2, 2, 0))
     assert tune.lookup("f32", 40, 200, 200, 200)[0] is False      # the form is in the key
-    assert tune.lookup("f64", 41, 200, 200, 200)[0] is False
+    # a view without an entry takes its shape class's: same form, layout, m
+    # and n, fiber count within a factor of two, the nearest in ratio
+    assert tune.lookup("f64", 41, 200, 200, 200) == (True, (7, 1, 8, 2, 2, 0))
+    assert tune.lookup("f64", 40, 200, 200, 399) == (True, (7, 1, 8, 2, 2, 0))
+    assert tune.lookup("f64", 40, 200, 200, 401)[0] is False      # 2.005 x the fibers
+    assert tune.lookup("f64", 40, 200, 200, 99)[0] is False
+    assert tune.lookup("f64", 1, 200, 200, 8000)[0] is False      # lead layout: own class
+    assert tune.lookup("f64", 40, 200, 208, 200)[0] is False      # n is in the class
+    tune.set_tile("f64", 40, 200, 200, 300, (4, 1, 16))
+    assert tune.lookup("f64", 40, 200, 200, 260)[1][:3] == (4, 1, 16)   # 1.15 x vs 1.3 x
+    assert tune.lookup("f64", 40, 200, 200, 240)[1][:3] == (7, 1, 8)    # 1.2 x vs 1.25 x
+    tune.set_tile("f64", 40, 200, 200, 300, (7, 1, 8, 2, 2))     # back to one class tile
+    assert lib.kp_tune_count() == 2
+    tune.clear()
+    tune.set_tile("f64", 40, 200, 200, 200, (7, 1, 8, 2, 2))
     tune.set_tile("bf16x3", 1, 30, 20, 1000, (2, 2, 32))
     ents = tune.entries()
     assert len(ents) == 2 == lib.kp_tune_count()
@@ -140,9 +154,24 @@ def test_save_load_round_trip(tune, tmp_path):
     tune.save(str(path))
     rec = json.loads(path.read_text())
     assert rec["entries"] == before
+    assert rec["variants"] == tune.variants_signature() and "arch" in rec
     tune.clear()
     assert tune.load(str(path)) == 2
     assert tune.entries() == before
+    # a table tuned for other compiled tiles, another device or another
+    # library version is refused unless forced
+    for key, value in (("variants", "0" * 16), ("arch", "gfx000"), ("kp_version", 1)):
+        bad = dict(rec, **{key: value})
+        if key == "arch" and tune.device_arch() is None:
+            continue                       # no device here: nothing to compare with
+        p2 = tmp_path / f"bad_{key}.json"
+        p2.write_text(json.dumps(bad))
+        tune.clear()
+        with pytest.raises(ValueError):
+            tune.load(str(p2))
+        assert tune.entries() == []
+        assert tune.load(str(p2), force=True) == 2
+    tune.clear()
 
 
 def views(m, n, order, backward=False):
@@ -242,8 +271,16 @@ def test_fusion_option_and_reported_launches(lib, L, tune):
         assert lib.kp_set_option(L.KP_OPT_FUSE, 0) == 0
         assert all(p["kind"] != 2 for p in tune.products(T, Ls, which="launches"))
         assert len(tune.products(T, Ls, which="launches")) == 5
-        # FP64 and the split forms are never fused
+        # six 16 -> 24 modes (the interpolation shape): pairs (2, 3) and (4, 5)
+        # of the 0-based steps move fewer elements than the first eligible
+        # pairs (1, 2), (3, 4) would (30.0 against 37.3 times 16^6)
         assert lib.kp_set_option(L.KP_OPT_FUSE, 1) == 0
+        T6 = torch.zeros((16,) * 6, dtype=torch.float32)
+        got6 = tune.products(T6, [torch.zeros((24, 16))] * 6, which="launches")
+        assert [p["kind"] == 2 for p in got6] == [False, False, True, True]
+        assert [(p["Il"], p["m"], p["n"]) for p in got6 if p["kind"] == 2] == \
+            [(24 * 24, 16, 24), (24 ** 4, 16, 24)]
+        # FP64 and the split forms are never fused
         T64 = T.double()
         L64 = [x.double() for x in Ls]
         assert all(p["kind"] != 2 for p in tune.products(T64, L64, which="launches"))
