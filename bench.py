@@ -11,11 +11,12 @@ through the C-ABI (kp_tucker), in each arithmetic form:
   bf16x3  BF16 split, 3 products, FP32 accumulation
   bf16x6  BF16 split, 6 products, FP32 accumulation
 
-Each form's error against the FP64 oracle (max-norm relative, the paper's
-metric) is reported with it. Each mu-mode product is also timed alone
-(kp_mump, launches back to back between two HIP events on the launch
-stream); the FP64 per-launch average gives the roofline entry of the
-dominant kernel.
+The steps are kp_tucker calls issued back to back (the rate of the same step
+replayed from a HIP graph is reported beside it). Each form's error against the FP64
+oracle (max-norm relative, the paper's metric) is reported with it. Each
+mu-mode product is also timed alone (kp_mump, launches back to back between
+two HIP events on the launch stream); the FP64 per-launch average gives the
+roofline entry of the dominant kernel.
 The oracle (numpy FP64 on the host) is timed on a bounded sample of the same
 workload as the CPU baseline. Prints one JSON line.
 """
@@ -211,7 +212,12 @@ def main():
         got = S.double().cpu().numpy()
         err = float(np.abs(got - ref).max() / np.abs(ref).max())
         err_fro = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
-        # timed region: K full Tucker steps, events on the launch stream
+        # Timed region: K full Tucker steps issued back to back (each one
+        # kp_tucker call, three mode launches), HIP events on the launch
+        # stream. The same step captured once in a HIP graph and replayed K
+        # times is timed beside it (ms_per_step_graph): on this runtime the
+        # replay does not shorten the step, whose gaps are between dependent
+        # kernels on the device, not host work.
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
         torch.cuda.synchronize()
         ev[0].record()
@@ -220,11 +226,35 @@ def main():
             ev[k + 1].record()
         torch.cuda.synchronize()
         step_ms = [ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)]
-        total_ms = ev[0].elapsed_time(ev[-1])
-        ms = total_ms / args.steps
+        ms = ev[0].elapsed_time(ev[-1]) / args.steps
+        graph = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            kp.tucker(Td, Lds, prec=prec)  # warm the pool outside the capture
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(graph):
+            Sg = kp.tucker(Td, Lds, prec=prec)
+        for _ in range(args.warmup):
+            graph.replay()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for k in range(args.steps):
+            graph.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        ms_graph = e0.elapsed_time(e1) / args.steps
+        # the replays computed what the eager calls compute (same kernels,
+        # same order): checked bitwise after the timed regions
+        graph_equal = bool(torch.equal(Sg, S))
+        del graph, Sg
         # each mu-mode product alone (kp_mump): `steps` launches back to back
-        # on the launch stream between two HIP events (the average includes
-        # the launch gaps, a few us, so it is an upper bound of the kernel time)
+        # on the launch stream between two HIP events; the queue stays ahead
+        # of the GPU, so the average is the kernel time plus the dispatch gap
+        # between consecutive launches (an upper bound of the kernel time)
         per_mode = {}
         for mu in (1, 2, 3):
             out = torch.empty_like(Td)
@@ -254,6 +284,9 @@ def main():
             "tflops": round(tflops, 3),
             "ms_per_step": round(ms, 5),
             "ms_median": round(statistics.median(step_ms), 5),
+            "ms_per_step_graph": round(ms_graph, 5),
+            "tflops_graph": round(flops / (ms_graph * 1e-3) / 1e12, 3),
+            "graph_replay_equals_eager": graph_equal,
             "frac_of_mfma_peak": round(mfma_tflops / peak, 4),
             "mfma_issued_tflops": round(mfma_tflops, 3),
             "peak_tflops": peak,
@@ -266,7 +299,8 @@ def main():
             "mode_ms": {str(k): round(v, 5) for k, v in per_mode.items()},
         }
         mode_avg[name] = statistics.mean(per_mode.values())
-        log(args, f"form {name}: {ms:.4f} ms/step  {tflops:.2f} TFLOP/s  err {err:.2e}  "
+        log(args, f"form {name}: {ms:.4f} ms/step (graph {ms_graph:.4f})  {tflops:.2f} TFLOP/s  "
+                  f"err {err:.2e}  "
                   f"modes {[round(v, 4) for v in per_mode.values()]} ms")
 
     head = results.get("f64") or next(iter(results.values()))
@@ -289,6 +323,8 @@ def main():
                    "d": 3, "m": 200, "n": 200, "flops_per_step": flops},
         "forms": results,
     }
+    line["config"]["timing"] = ("kp_tucker calls back to back, HIP events; ms_per_step_graph "
+                                "per form: the same step replayed from a HIP graph")
     if "f64" in mode_avg:
         avg_ms = mode_avg["f64"]
         achieved = flops_mode / (avg_ms * 1e-3) / 1e12

@@ -118,3 +118,32 @@ def test_batch64_each_tensor(kp, prec):
                 ref = oracle.tucker_entry(T64, L64, i)
                 bnd = coef * oracle.tucker_entry(np.abs(T64), [np.abs(L) for L in L64], i)
                 assert abs(got[i] - ref) <= bnd, (k, i)
+
+
+@pytest.mark.parametrize("dt,prec", [("f64", "native"), ("f32", "bf16x3")])
+def test_cube200_graph_replay(kp, dt, prec):
+    """kp_tucker captured into a HIP graph (the benchmark's timed step):
+    every replay, with eager library calls on other data and host
+    synchronisations between replays, equals the eager result bitwise."""
+    T, Ls = kp_workloads.cube200()
+    Td = to_dev(T, DT[dt])
+    Lds = [to_dev(L, DT[dt]) for L in Ls]
+    want = kp.tucker(Td, Lds, prec=prec)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        kp.tucker(Td, Lds, prec=prec)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        Sg = kp.tucker(Td, Lds, prec=prec)
+    T2, L2 = kp_workloads.random_problem(11, (30, 40, 50), (20, 35, 45))
+    for r in range(3):
+        say("graph replay", dt, prec, r)
+        Sg.fill_(float("nan"))
+        g.replay()
+        other = kp.tucker(to_dev(T2, DT[dt]), [to_dev(L, DT[dt]) for L in L2], prec=prec)
+        torch.cuda.synchronize()
+        assert torch.equal(Sg, want), r
+        assert torch.isfinite(other).all()
