@@ -1,7 +1,8 @@
 // Fused pairs of consecutive mu-mode products (pair_tile.h), FP32 form:
 // the memory-bound products of short modes (m <= 16, n <= 32) on the
 // strided layout (I_l > 1). One launch per piece of the outer index b that
-// stays below 2^31 bytes; workgroups stride over 16-fiber tiles.
+// stays below 2^31 bytes; workgroups stride over 64-fiber tiles (16 fibers
+// per wave).
 #include <mutex>
 #include <unordered_map>
 
@@ -14,12 +15,12 @@ namespace {
 
 using namespace tile;
 
-constexpr int kKP1 = 16, kKP2 = 16, kNB1 = 2, kNB2 = 2;
+constexpr int kNB1 = 2, kNB2 = 2;
+static_assert(kThreads == 64 * kPairWaves, "one fiber group per wave");
 
 __global__ __launch_bounds__(kThreads, 2) void pair_kernel_f32(PairArgs a, int64_t ntiles) {
-  __shared__ __attribute__((aligned(16))) char
-      lds[pair_lds_bytes<FORM_F32, kKP1, kKP2, kNB1, kNB2>()];
-  pair_run<FORM_F32, kKP1, kKP2, kNB1, kNB2>(a, blockIdx.x, gridDim.x, ntiles, lds);
+  __shared__ __attribute__((aligned(16))) char lds[kPairLdsBytes];
+  pair_run<kNB1, kNB2>(a, blockIdx.x, gridDim.x, ntiles, lds);
 }
 
 int pair_slots() {
@@ -44,7 +45,7 @@ int pair_slots() {
 }  // namespace
 
 bool pair_eligible(int form, int64_t Il, int64_t m1, int64_t m2, int64_t n1, int64_t n2) {
-  return form == FORM_F32 && Il > 1 && m1 >= 1 && m2 >= 1 && m1 <= kKP1 && m2 <= kKP2 &&
+  return form == FORM_F32 && Il > 1 && m1 >= 1 && m2 >= 1 && m1 <= kPairK && m2 <= kPairK &&
          n1 >= 1 && n2 >= 1 && n1 <= 16 * kNB1 && n2 <= 16 * kNB2;
 }
 
@@ -62,7 +63,8 @@ hipError_t launch_pair(int form, const PairArgs& a, hipStream_t stream) {
     p.Ir = (a.Ir - b0 < per) ? a.Ir - b0 : per;
     p.X = static_cast<const char*>(a.X) + b0 * a.Il * mm * es;
     p.Y = static_cast<char*>(a.Y) + b0 * a.Il * nn * es;
-    const int64_t ntiles = (p.Il * p.Ir + kPairFibers - 1) / kPairFibers;
+    const int64_t per_tile = kPairWaves * kPairFibers;
+    const int64_t ntiles = (p.Il * p.Ir + per_tile - 1) / per_tile;
     int64_t grid = pair_slots();
     if (grid > ntiles) grid = ntiles;
     hipLaunchKernelGGL(pair_kernel_f32, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0,

@@ -8,15 +8,20 @@
 // X[r; j1, j2] sits at base(r, m1*m2) + Il*(j1 + m1*j2) with
 // base(r, len) = (r % Il) + Il*len*(r / Il); Y likewise with n1, n2.
 //
-// A workgroup keeps L1 and L2 in LDS and streams tiles of 16 fibers: the
-// tile's X goes to LDS (the next tile's global loads are in flight meanwhile),
-// stage 1 writes Z to LDS (the waves split the j2 values), stage 2 reads it
-// and writes Y straight to HBM (the waves split the i1 values). Fibers are
-// the MFMA columns, so every store is a run of consecutive fibers; the
-// kernel is meant for Il > 1, where consecutive fibers are contiguous.
+// FP32 form. Every wave works alone on 16 consecutive fibers at a time (the
+// MFMA columns), so no barrier is ever needed:
+//   - the MFMA operands of L1 and L2 are loaded once into registers;
+//   - a wave's X values go straight from global memory into the stage-1
+//     operand registers (each X value feeds exactly one product, so staging
+//     through LDS would buy nothing); the next fiber group's values are
+//     loaded while the current one is computed;
+//   - stage 1 writes Z for 16 rows i1 at a time into the wave's own LDS
+//     block, stage 2 reads it back as its operand and stores Y directly.
+// The four waves of a workgroup take four adjacent fiber groups, so each
+// row of X and Y is read and written in runs of 64 consecutive fibers.
 // Each output element is summed over j1, then j2, in the same order and
-// precision as two separate mu-mode products, with Z rounded to the
-// element type in between (FP32 for the split forms, re-split on use).
+// precision as two separate mu-mode products (one 16-long macro step each,
+// Z rounded to FP32 in between), so fused and unfused results are equal.
 #pragma once
 
 #include "mode_tile.h"
@@ -24,29 +29,12 @@
 namespace kp {
 namespace tile {
 
-constexpr int kPairFibers = 16;
-
-// KP1 >= m1, KP2 >= m2 (multiples of the macro step), NB1*16 >= n1,
-// NB2*16 >= n2.
-template <int FORM, int KP1, int KP2, int NB1, int NB2>
-struct PairLayout {
-  using FT = FormT<FORM>;
-  using SE = typename FT::S;
-  static constexpr int P = FT::P;
-  static constexpr int BF = kPairFibers;
-  static constexpr int LD1 = KP1 + 16 / sizeof(SE);   // sX rows: j1 contiguous
-  static constexpr int LD2 = KP2 + 16 / sizeof(SE);   // sZ rows: j2 contiguous
-  static constexpr size_t l1 = sizeof(SE) * P * (16 * NB1) * LD1;
-  static constexpr size_t l2 = sizeof(SE) * P * (16 * NB2) * LD2;
-  static constexpr size_t x = sizeof(SE) * P * KP2 * BF * LD1;        // [p][j2][f][j1]
-  static constexpr size_t z = sizeof(SE) * P * (16 * NB1) * BF * LD2; // [p][i1][f][j2]
-  static constexpr size_t bytes = l1 + l2 + x + z;
-};
-
-template <int FORM, int KP1, int KP2, int NB1, int NB2>
-constexpr size_t pair_lds_bytes() {
-  return PairLayout<FORM, KP1, KP2, NB1, NB2>::bytes;
-}
+constexpr int kPairK = 16;        // m1, m2 <= 16
+constexpr int kPairFibers = 16;   // fibers per wave group
+constexpr int kPairWaves = 4;     // waves per workgroup
+// LDS: per wave, Z for 16 rows i1 x 16 fibers x 16 j2 (FP32), no padding:
+// the four 16-byte j2 slots of a (row, fiber) are XOR-swizzled by the fiber
+constexpr size_t kPairLdsBytes = kPairWaves * 16 * kPairFibers * kPairK * sizeof(float);
 
 struct PairArgs {
   const void* X;
@@ -57,226 +45,166 @@ struct PairArgs {
   int64_t rs1, cs1, rs2, cs2;
 };
 
-// Fiber tiles t0, t0 + tstep, ... < ntiles (16 fibers each).
-template <int FORM, int KP1, int KP2, int NB1, int NB2>
-__device__ __forceinline__ void pair_run(const PairArgs& a, int64_t t0, int64_t tstep,
+// NB1*16 >= n1, NB2*16 >= n2. Workgroup tiles tile0, tile0 + tstep, ... <
+// ntiles; tile k covers fibers 64k .. 64k + 63, wave w of the workgroup the
+// 16 fibers 64k + 16w .. 64k + 16w + 15.
+template <int NB1, int NB2>
+__device__ __forceinline__ void pair_run(const PairArgs& a, int64_t tile0, int64_t tstep,
                                          int64_t ntiles, char* __restrict__ lds) {
-  using LY = PairLayout<FORM, KP1, KP2, NB1, NB2>;
-  using FT = FormT<FORM>;
-  using G = typename FT::G;
-  using SE = typename FT::S;
-  using acc_t = typename FT::acc_t;
-  using FragT = Frag<FORM>;
-  constexpr int P = FT::P, KV = FT::KV, MK = FT::MK;
-  constexpr bool SPLIT = FORM == FORM_BF16X3 || FORM == FORM_BF16X6;
-  constexpr int BF = LY::BF, LD1 = LY::LD1, LD2 = LY::LD2;
-  constexpr int R1 = 16 * NB1, R2 = 16 * NB2;
-  constexpr int KG1 = KP1 / KV;
-  // X staging tasks: (fiber, j1 group, j2); lanes walk along fibers
-  constexpr int XTASKS = BF * KG1 * KP2;
-  constexpr int XT = (XTASKS + kThreads - 1) / kThreads;
-  static_assert(KP1 % MK == 0 && KP2 % MK == 0, "contraction lengths need whole macro steps");
+  using acc_t = f4_t;
+  using FragT = f4v_t;
+  const int t = threadIdx.x;
+  const int lane = t & 63;
+  const int w = t >> 6;
+  const int c = lane & 15;  // MFMA column: fiber within the group
+  const int g = lane >> 4;  // lane group: k values 4g .. 4g + 3 of a macro step
+  float* __restrict__ zw = reinterpret_cast<float*>(lds) + w * (16 * kPairFibers * kPairK);
 
-  typedef SE L1T[P][R1][LD1];
-  typedef SE L2T[P][R2][LD2];
-  typedef SE XTl[P][KP2][BF][LD1];
-  typedef SE ZTl[P][R1][BF][LD2];
-  L1T& sL1 = *reinterpret_cast<L1T*>(lds);
-  L2T& sL2 = *reinterpret_cast<L2T*>(lds + LY::l1);
-  XTl& sX = *reinterpret_cast<XTl*>(lds + LY::l1 + LY::l2);
-  ZTl& sZ = *reinterpret_cast<ZTl*>(lds + LY::l1 + LY::l2 + LY::x);
-
-  const G* __restrict__ L1 = static_cast<const G*>(a.L1);
-  const G* __restrict__ L2 = static_cast<const G*>(a.L2);
   // 32-bit index math: the host keeps every launch below 2^31 bytes
   const uint32_t Il = static_cast<uint32_t>(a.Il);
   const uint32_t m1 = static_cast<uint32_t>(a.m1), m2 = static_cast<uint32_t>(a.m2);
   const uint32_t n1 = static_cast<uint32_t>(a.n1), n2 = static_cast<uint32_t>(a.n2);
   const uint32_t F = static_cast<uint32_t>(a.Il * a.Ir);
-  const int t = threadIdx.x;
-  const int lane = t & 63;
-  const int w = t >> 6;
-  const int c = lane & 15;
-  const int g = lane >> 4;
+  constexpr uint32_t kOut = 0x80000000u;  // >= any resource size here
 
-  auto put = [&](SE* dst0, size_t plane, const G (&v)[KV]) {
-    // KV consecutive k values of one row into every plane (16 bytes each)
-    if constexpr (SPLIT) {
-      bf16x8_t pl[P];
+  // Operands of L1 (rows i1 = 16 q + c, k = j1 = 4g + s) and L2 (rows
+  // i2 = 16 q + c, k = j2 = 4g + s), zero past n or m: fixed for the kernel.
+  FragT l1f[NB1], l2f[NB2];
+  const float* L1 = static_cast<const float*>(a.L1);
+  const float* L2 = static_cast<const float*>(a.L2);
 #pragma unroll
-      for (int e = 0; e < KV; ++e) {
-        __bf16 o[P];
-        split_bf16<P>(v[e], o);
+  for (int q = 0; q < NB1; ++q)
 #pragma unroll
-        for (int p = 0; p < P; ++p) pl[p][e] = o[p];
-      }
-#pragma unroll
-      for (int p = 0; p < P; ++p) *reinterpret_cast<bf16x8_t*>(dst0 + p * plane) = pl[p];
-    } else {
-      FragT f;
-#pragma unroll
-      for (int e = 0; e < KV; ++e) f[e] = v[e];
-      *reinterpret_cast<FragT*>(dst0) = f;
+    for (int s = 0; s < 4; ++s) {
+      const uint32_t i = 16 * q + c, k = 4 * g + s;
+      l1f[q][s] = (i < n1 && k < m1) ? L1[i * a.rs1 + k * a.cs1] : 0.0f;
     }
-  };
+#pragma unroll
+  for (int q = 0; q < NB2; ++q)
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const uint32_t i = 16 * q + c, k = 4 * g + s;
+      l2f[q][s] = (i < n2 && k < m2) ? L2[i * a.rs2 + k * a.cs2] : 0.0f;
+    }
 
-  // factors -> LDS once (k >= m and rows >= n read as zero)
-  for (int id = t; id < R1 * KG1; id += kThreads) {
-    const int i = id / KG1, kg = id % KG1;
-    G v[KV];
-#pragma unroll
-    for (int e = 0; e < KV; ++e) {
-      const uint32_t k = kg * KV + e;
-      v[e] = (static_cast<uint32_t>(i) < n1 && k < m1) ? L1[i * a.rs1 + k * a.cs1] : G(0);
-    }
-    put(&sL1[0][i][kg * KV], R1 * LD1, v);
-  }
-  for (int id = t; id < R2 * (KP2 / KV); id += kThreads) {
-    const int i = id / (KP2 / KV), kg = id % (KP2 / KV);
-    G v[KV];
-#pragma unroll
-    for (int e = 0; e < KV; ++e) {
-      const uint32_t k = kg * KV + e;
-      v[e] = (static_cast<uint32_t>(i) < n2 && k < m2) ? L2[i * a.rs2 + k * a.cs2] : G(0);
-    }
-    put(&sL2[0][i][kg * KV], R2 * LD2, v);
-  }
-
-  G xr[XT][KV];
-  // X tile -> registers through a buffer resource (32-bit offsets): task =
-  // (fiber f, j1 group kg, j2); a j1 or j2 past m1, m2 gets an offset past the
-  // resource and reads as zero; fibers past F are clamped (their outputs are
-  // never stored). Y is written through a resource too.
-  constexpr uint32_t kOut = 0x80000000u;
   const auto xrs = __builtin_amdgcn_make_buffer_rsrc(
-      const_cast<void*>(a.X), 0, static_cast<int>(a.Il * a.m1 * a.m2 * a.Ir * sizeof(G)),
+      const_cast<void*>(a.X), 0, static_cast<int>(a.Il * a.m1 * a.m2 * a.Ir * sizeof(float)),
       kBufferFlags);
   const auto yrs = __builtin_amdgcn_make_buffer_rsrc(
-      a.Y, 0, static_cast<int>(a.Il * a.n1 * a.n2 * a.Ir * sizeof(G)), kBufferFlags);
-  auto load_x = [&](int64_t bx) {
-    const uint32_t f0 = static_cast<uint32_t>(bx) * BF;
+      a.Y, 0, static_cast<int>(a.Il * a.n1 * a.n2 * a.Ir * sizeof(float)), kBufferFlags);
+  const uint32_t xstep = Il * 4;  // bytes per unit of j1
+
+  // Stage-1 operand of X for j2 and step s: X[r; j1 = 4g + s, j2] of this
+  // lane's fiber r (zero past m1, m2; fibers past F read the last fiber,
+  // whose outputs are never stored).
+  // Full modes (m1 = m2 = 16): one per-lane offset, the (s, j2) step as the
+  // loads' scalar offset; otherwise per-element offsets, k past m reading zero.
+  const bool full = m1 == kPairK && m2 == kPairK;
+  auto load_x = [&](int64_t tile, float (&xr)[kPairK][4]) {
+    uint32_t r = static_cast<uint32_t>(tile) * (kPairWaves * kPairFibers) + w * kPairFibers + c;
+    r = r < F ? r : F - 1;
+    const uint32_t b = r / Il;
+    const uint32_t base = ((r - b * Il) + Il * m1 * m2 * b) * 4 + xstep * (4 * g);
+    if (full) {
+      uint32_t vj = base;  // offset of (j1 = 4g, j2)
 #pragma unroll
-    for (int s = 0; s < XT; ++s) {
-      const int id = t + s * kThreads;
-      const int f = id % BF;
-      const int kg = (id / BF) % KG1;
-      const uint32_t j2 = id / (BF * KG1);
-      uint32_t r = f0 + f;
-      r = r < F ? r : F - 1;
-      const uint32_t b = r / Il;
-      const uint32_t base = (r - b * Il) + Il * m1 * m2 * b + Il * m1 * j2;
+      for (int j2 = 0; j2 < kPairK; ++j2, vj += kPairK * xstep)
 #pragma unroll
-      for (int e = 0; e < KV; ++e) {
-        const uint32_t j1 = kg * KV + e;
-        xr[s][e] = buffer_load<G>(
-            xrs, (id < XTASKS && j1 < m1 && j2 < m2) ? (base + Il * j1) * sizeof(G) : kOut);
+        for (int s = 0; s < 4; ++s) xr[j2][s] = buffer_load<float>(xrs, vj, xstep * s);
+    } else {
+      uint32_t vj = base;
+#pragma unroll
+      for (int j2 = 0; j2 < kPairK; ++j2, vj += m1 * xstep) {
+        if (static_cast<uint32_t>(j2) >= m2) {
+#pragma unroll
+          for (int s = 0; s < 4; ++s) xr[j2][s] = 0.0f;
+          continue;
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+          xr[j2][s] = buffer_load<float>(
+              xrs, 4 * g + s < static_cast<int>(m1) ? vj + s * xstep : kOut);
       }
     }
   };
-  auto store_x = [&]() {
-#pragma unroll
-    for (int s = 0; s < XT; ++s) {
-      const int id = t + s * kThreads;
-      if (id >= XTASKS) continue;
-      const int f = id % BF;
-      const int kg = (id / BF) % KG1;
-      const int j2 = id / (BF * KG1);
-      put(&sX[0][j2][f][kg * KV], KP2 * BF * LD1, xr[s]);
-    }
+  // Z of (row i1 local, fiber c) holds 16 j2 values as four 16-byte slots;
+  // slot u sits at position u ^ (c >> 2 & 3), so the 16 fibers of one lane
+  // group read 16 different bank groups
+  auto zslot = [&](int row, int u) {
+    return zw + (row * kPairFibers + c) * kPairK + 4 * (u ^ ((c >> 2) & 3));
   };
 
-  if (t0 < ntiles) {
-    load_x(t0);
-    store_x();
-  }
-  __syncthreads();
-  for (int64_t bx = t0; bx < ntiles; bx += tstep) {
-    const int64_t nx = bx + tstep;
-    if (nx < ntiles) load_x(nx);
-    // stage 1: Z[i1][f][j2] for the j2 of this wave (w, w + 4, ...)
-    for (int j2 = w; j2 < KP2; j2 += 4) {
-      acc_t hi[NB1][1], lo[NB1][1];
+  float xa[kPairK][4], xb[kPairK][4];
+  auto run = [&](int64_t tile, float (&xr)[kPairK][4]) {
+    const uint32_t r = static_cast<uint32_t>(tile) * (kPairWaves * kPairFibers) +
+                       w * kPairFibers + c;
+    const uint32_t rr = r < F ? r : 0;
+    const uint32_t rb = rr / Il;
+    const uint32_t ybase = (rr - rb * Il) + Il * n1 * n2 * rb;
 #pragma unroll
-      for (int q = 0; q < NB1; ++q) {
-        hi[q][0] = acc_t{};
-        lo[q][0] = acc_t{};
-      }
+    for (int q = 0; q < NB1; ++q) {
+      if (16u * q >= n1) break;
+      // stage 1: Z[i1 = 16q + 4g + v][c][j2] for all 16 j2 (4 at a time)
 #pragma unroll
-      for (int kk = 0; kk < KP1; kk += MK) {
-        FragT xb[1][P];
-        FragT la[NB1][P];
+      for (int u = 0; u < kPairK / 4; ++u) {
+        acc_t z[4];
 #pragma unroll
-        for (int p = 0; p < P; ++p)
-          xb[0][p] = *reinterpret_cast<const FragT*>(&sX[p][j2][c][kk + KV * g]);
+        for (int e = 0; e < 4; ++e) z[e] = acc_t{};
 #pragma unroll
-        for (int q = 0; q < NB1; ++q)
+        for (int s = 0; s < 4; ++s)
 #pragma unroll
-          for (int p = 0; p < P; ++p)
-            la[q][p] = *reinterpret_cast<const FragT*>(&sL1[p][q * 16 + c][kk + KV * g]);
-        macro_step_grid<FORM, NB1, 1>(la, xb, hi, lo);
-      }
-      // rows i1 = q*16 + row(lane, v), column f = c; Z rounded to G, split
-      // into the planes when the form has them
-#pragma unroll
-      for (int q = 0; q < NB1; ++q) {
-        acc_t val = hi[q][0];
-        if constexpr (SPLIT) val = hi[q][0] + lo[q][0];
+          for (int e = 0; e < 4; ++e)
+            z[e] = __builtin_amdgcn_mfma_f32_16x16x4f32(l1f[q][s], xr[4 * u + e][s], z[e], 0, 0,
+                                                        0);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int i1 = q * 16 + FT::row(lane, v);
-          const G z = static_cast<G>(val[v]);
-          if constexpr (SPLIT) {
-            __bf16 o[P];
-            split_bf16<P>(z, o);
+          const f4v_t val = {z[0][v], z[1][v], z[2][v], z[3][v]};
+          *reinterpret_cast<f4v_t*>(zslot(4 * g + v, u)) = val;
+        }
+      }
+      // the wave's own LDS writes above precede its reads below
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      // stage 2: Y[r; i1, i2] for the rows i1 of this block
+      const uint32_t rows = n1 - 16 * q < 16 ? n1 - 16 * q : 16;
+      for (uint32_t il = 0; il < rows; ++il) {
+        const FragT zf = *reinterpret_cast<const FragT*>(zslot(il, g));
+        acc_t y[NB2];
 #pragma unroll
-            for (int p = 0; p < P; ++p) sZ[p][i1][c][j2] = o[p];
-          } else {
-            sZ[0][i1][c][j2] = z;
+        for (int q2 = 0; q2 < NB2; ++q2) y[q2] = acc_t{};
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+          for (int q2 = 0; q2 < NB2; ++q2)
+            y[q2] = __builtin_amdgcn_mfma_f32_16x16x4f32(l2f[q2][s], zf[s], y[q2], 0, 0, 0);
+        const uint32_t i1 = 16 * q + il;
+#pragma unroll
+        for (int q2 = 0; q2 < NB2; ++q2)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const uint32_t i2 = 16 * q2 + 4 * g + v;
+            buffer_store<float>(y[q2][v], yrs,
+                                (r < F && i2 < n2) ? (ybase + Il * (i1 + n1 * i2)) * 4 : kOut);
           }
-        }
       }
+      // the reads above precede the next block's writes
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    __syncthreads();  // Z complete, X reads done
-    if (nx < ntiles) store_x();
-    // stage 2: Y for the i1 of this wave (w, w + 4, ...)
-    const uint32_t f0 = static_cast<uint32_t>(bx) * BF;
-    const uint32_t r = f0 + c;
-    const uint32_t rb = r / Il;
-    const uint32_t ybase = (r - rb * Il) + Il * n1 * n2 * rb;
-    for (int i1 = w; i1 < static_cast<int>(n1); i1 += 4) {
-      acc_t hi[NB2][1], lo[NB2][1];
-#pragma unroll
-      for (int q = 0; q < NB2; ++q) {
-        hi[q][0] = acc_t{};
-        lo[q][0] = acc_t{};
-      }
-#pragma unroll
-      for (int kk = 0; kk < KP2; kk += MK) {
-        FragT zb[1][P];
-        FragT la[NB2][P];
-#pragma unroll
-        for (int p = 0; p < P; ++p)
-          zb[0][p] = *reinterpret_cast<const FragT*>(&sZ[p][i1][c][kk + KV * g]);
-#pragma unroll
-        for (int q = 0; q < NB2; ++q)
-#pragma unroll
-          for (int p = 0; p < P; ++p)
-            la[q][p] = *reinterpret_cast<const FragT*>(&sL2[p][q * 16 + c][kk + KV * g]);
-        macro_step_grid<FORM, NB2, 1>(la, zb, hi, lo);
-      }
-#pragma unroll
-      for (int q = 0; q < NB2; ++q) {
-        acc_t val = hi[q][0];
-        if constexpr (SPLIT) val = hi[q][0] + lo[q][0];
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const uint32_t i2 = q * 16 + FT::row(lane, v);
-          buffer_store<G>(val[v], yrs,
-                          (r < F && i2 < n2) ? (ybase + Il * (i1 + n1 * i2)) * sizeof(G) : kOut);
-        }
-      }
-    }
-    __syncthreads();  // Z reads done; the next tile's X is in LDS
+  };
+  // workgroup tiles tile0, tile0 + tstep, ...; two register sets alternate so
+  // the next tile's X is in flight while the current one is computed
+  int64_t tile = tile0;
+  if (tile < ntiles) load_x(tile, xa);
+  while (tile < ntiles) {
+    const int64_t nx = tile + tstep;
+    if (nx < ntiles) load_x(nx, xb);
+    run(tile, xa);
+    if (nx >= ntiles) break;
+    const int64_t nx2 = nx + tstep;
+    if (nx2 < ntiles) load_x(nx2, xa);
+    run(nx, xb);
+    tile = nx2;
   }
 }
 
