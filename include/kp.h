@@ -278,8 +278,11 @@ int kp_tucker_batched(const void* plan_dev, const void* plan, void* ws, size_t w
  * E_k = exp(tau * A_k) for `count` n x n column-major FP64 matrices stored one
  * after another in A (device memory); E receives them in the same layout.
  * n <= 256. Scaling and squaring with the degree-13 diagonal Pade approximant
- * (Higham 2005), all steps on the device (one workgroup per matrix), so the
- * call never synchronises. ws_bytes >= kp_expm_workspace(n, count).
+ * (Higham 2005), all steps on the device as a fixed sequence of launches on
+ * `stream` (the scaling exponent stays in the workspace; the products run
+ * over 32 x 32 tiles of every matrix, the Pade solve and any squarings past
+ * the eighth in one workgroup per matrix), so the call never synchronises.
+ * ws_bytes >= kp_expm_workspace(n, count).
  * Errors: KP_ERR_SHAPE (n < 0, n > 256, count < 0), KP_ERR_NULL,
  * KP_ERR_VALUE (tau not finite), KP_ERR_WORKSPACE, KP_ERR_ALIAS (E overlaps
  * A or the workspace). A singular Pade denominator (impossible for finite

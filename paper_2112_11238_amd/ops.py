@@ -271,7 +271,7 @@ def tucker_autograd(T, Ls, prec="native", cache_partials=True):
 def expm(A, tau=1.0):
     """exp(tau * A) in FP64 on the device for a square matrix A (n <= 256) or
     a batch of them (shape (count, n, n)). Scaling and squaring with the
-    degree-13 Pade approximant, all in one launch (kp_expm_f64)."""
+    degree-13 Pade approximant, every step on the device (kp_expm_f64)."""
     _check_device(A)
     if A.dtype != torch.float64:
         raise TypeError("expm runs in float64")

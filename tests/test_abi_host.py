@@ -294,7 +294,8 @@ def test_backward_cache_and_output_alias_errors(lib, L):
 @no_device
 def test_expm_argument_errors(lib):
     ws = lib.kp_expm_workspace(128, 3)
-    assert ws == 8 * 128 * 128 * 3 * 8
+    # eight n x n FP64 slots per matrix, then one int per matrix (256-byte aligned)
+    assert ws == 8 * 128 * 128 * 3 * 8 + 256
     assert lib.kp_expm_f64(FAKE, 300, 1, 1.0, FAKE * 2, FAKE * 4, 10 ** 9, None) == -4
     assert lib.kp_expm_f64(None, 4, 1, 1.0, FAKE, FAKE * 4, 10 ** 6, None) == -1
     assert lib.kp_expm_f64(FAKE, 4, 1, float("nan"), FAKE * 2, FAKE * 4, 10 ** 6, None) == -9
