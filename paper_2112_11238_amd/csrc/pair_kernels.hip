@@ -1,4 +1,5 @@
-// Fused pairs of consecutive mu-mode products (pair_tile.h), FP32 form:
+// Fused pairs of consecutive mu-mode products (pair_tile.h), FP32 and the
+// BF16 split forms:
 // the memory-bound products of short modes (m <= 16, n <= 32) on the
 // strided layout (I_l > 1). One launch per piece of the outer index b that
 // stays below 2^31 bytes; workgroups stride over 64-fiber tiles (16 fibers
@@ -18,9 +19,10 @@ using namespace tile;
 constexpr int kNB1 = 2, kNB2 = 2;
 static_assert(kThreads == 64 * kPairWaves, "one fiber group per wave");
 
-__global__ __launch_bounds__(kThreads, 2) void pair_kernel_f32(PairArgs a, int64_t ntiles) {
+template <int FORM>
+__global__ __launch_bounds__(kThreads, 2) void pair_kernel(PairArgs a, int64_t ntiles) {
   __shared__ __attribute__((aligned(16))) char lds[kPairLdsBytes];
-  pair_run<kNB1, kNB2>(a, blockIdx.x, gridDim.x, ntiles, lds);
+  pair_run<FORM, kNB1, kNB2>(a, blockIdx.x, gridDim.x, ntiles, lds);
 }
 
 int pair_slots() {
@@ -34,7 +36,8 @@ int pair_slots() {
         cus < 1)
       cus = 256;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per, reinterpret_cast<const void*>(pair_kernel_f32), kThreads, 0) != hipSuccess ||
+            &per, reinterpret_cast<const void*>(pair_kernel<FORM_F32>), kThreads, 0) !=
+            hipSuccess ||
         per < 1)
       per = 1;
     slots = cus * per;
@@ -45,7 +48,7 @@ int pair_slots() {
 }  // namespace
 
 bool pair_eligible(int form, int64_t Il, int64_t m1, int64_t m2, int64_t n1, int64_t n2) {
-  return form == FORM_F32 && Il > 1 && m1 >= 1 && m2 >= 1 && m1 <= kPairK && m2 <= kPairK &&
+  return (form == FORM_F32 || form == FORM_BF16X3 || form == FORM_BF16X6) && Il > 1 && m1 >= 1 && m2 >= 1 && m1 <= kPairK && m2 <= kPairK &&
          n1 >= 1 && n2 >= 1 && n1 <= 16 * kNB1 && n2 <= 16 * kNB2;
 }
 
@@ -67,8 +70,11 @@ hipError_t launch_pair(int form, const PairArgs& a, hipStream_t stream) {
     const int64_t ntiles = (p.Il * p.Ir + per_tile - 1) / per_tile;
     int64_t grid = pair_slots();
     if (grid > ntiles) grid = ntiles;
-    hipLaunchKernelGGL(pair_kernel_f32, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0,
-                       stream, p, ntiles);
+    void (*kern)(PairArgs, int64_t) = form == FORM_F32      ? pair_kernel<FORM_F32>
+                                      : form == FORM_BF16X3 ? pair_kernel<FORM_BF16X3>
+                                                            : pair_kernel<FORM_BF16X6>;
+    hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0, stream, p,
+                       ntiles);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -8,8 +8,12 @@
 // X[r; j1, j2] sits at base(r, m1*m2) + Il*(j1 + m1*j2) with
 // base(r, len) = (r % Il) + Il*len*(r / Il); Y likewise with n1, n2.
 //
-// FP32 form. Every wave works alone on 16 consecutive fibers at a time (the
-// MFMA columns), so no barrier is ever needed:
+// FP32 (v_mfma_f32_16x16x4, four per 16-long macro step) and the BF16 split
+// forms (v_mfma_f32_16x16x16_bf16 on the two or three bf16 planes of each
+// operand, split in registers by round-to-nearest-even, the leading product
+// in one FP32 accumulator and the correction products in another). Every
+// wave works alone on 16 consecutive fibers at a time (the MFMA columns), so
+// no barrier is ever needed:
 //   - the MFMA operands of L1 and L2 are loaded once into registers;
 //   - a wave's X values go straight from global memory into the stage-1
 //     operand registers (each X value feeds exactly one product, so staging
@@ -19,9 +23,12 @@
 //     block, stage 2 reads it back as its operand and stores Y directly.
 // The four waves of a workgroup take four adjacent fiber groups, so each
 // row of X and Y is read and written in runs of 64 consecutive fibers.
-// Each output element is summed over j1, then j2, in the same order and
-// precision as two separate mu-mode products (one 16-long macro step each,
-// Z rounded to FP32 in between), so fused and unfused results are equal.
+// Each output element is summed over j1, then j2, with Z rounded to FP32 in
+// between as in two separate mu-mode products. In FP32 the products and
+// their order are those of the unfused kernels (one 16-long macro step), so
+// fused and unfused results are equal; the BF16 forms take the 16-long bf16
+// MFMA here where the unfused kernels zero-pad a 32-long one, so their sums
+// agree to rounding, within the same error bound.
 #pragma once
 
 #include "mode_tile.h"
@@ -48,11 +55,50 @@ struct PairArgs {
 // NB1*16 >= n1, NB2*16 >= n2. Workgroup tiles tile0, tile0 + tstep, ... <
 // ntiles; tile k covers fibers 64k .. 64k + 63, wave w of the workgroup the
 // 16 fibers 64k + 16w .. 64k + 16w + 15.
-template <int NB1, int NB2>
+// bf16 operand of the 16x16x16 MFMA: lane l holds k = 4 (l / 16) .. + 3 of
+// row (A) or column (B) l mod 16
+typedef short pair_s4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 pair_b4_t __attribute__((ext_vector_type(4)));
+
+template <int FORM>
+struct PairPlanes {
+  static constexpr int P = FORM == FORM_BF16X6 ? 3 : 2;
+  pair_s4_t p[P];
+};
+
+// The P bf16 planes of four consecutive k values.
+template <int FORM>
+__device__ __forceinline__ PairPlanes<FORM> pair_split(const f4v_t& v) {
+  PairPlanes<FORM> out;
+  const float x[4] = {v[0], v[1], v[2], v[3]};
+  pair_b4_t pl[PairPlanes<FORM>::P];
+  split_bf16_group<PairPlanes<FORM>::P, 4>(x, pl);
+#pragma unroll
+  for (int q = 0; q < PairPlanes<FORM>::P; ++q) out.p[q] = __builtin_bit_cast(pair_s4_t, pl[q]);
+  return out;
+}
+
+// One 16-long macro step of the split products into (hi, lo): the
+// correction products (smallest first) into lo, the leading one into hi.
+template <int FORM>
+__device__ __forceinline__ void pair_mma(const PairPlanes<FORM>& A, const PairPlanes<FORM>& B,
+                                         f4_t& hi, f4_t& lo) {
+  if constexpr (FORM == FORM_BF16X6) {
+    lo = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A.p[0], B.p[2], lo, 0, 0, 0);
+    lo = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A.p[1], B.p[1], lo, 0, 0, 0);
+    lo = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A.p[2], B.p[0], lo, 0, 0, 0);
+  }
+  lo = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A.p[0], B.p[1], lo, 0, 0, 0);
+  lo = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A.p[1], B.p[0], lo, 0, 0, 0);
+  hi = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A.p[0], B.p[0], hi, 0, 0, 0);
+}
+
+template <int FORM, int NB1, int NB2>
 __device__ __forceinline__ void pair_run(const PairArgs& a, int64_t tile0, int64_t tstep,
                                          int64_t ntiles, char* __restrict__ lds) {
   using acc_t = f4_t;
   using FragT = f4v_t;
+  constexpr bool SPLIT = FORM != FORM_F32;
   const int t = threadIdx.x;
   const int lane = t & 63;
   const int w = t >> 6;
@@ -86,6 +132,14 @@ __device__ __forceinline__ void pair_run(const PairArgs& a, int64_t tile0, int64
       const uint32_t i = 16 * q + c, k = 4 * g + s;
       l2f[q][s] = (i < n2 && k < m2) ? L2[i * a.rs2 + k * a.cs2] : 0.0f;
     }
+
+  PairPlanes<FORM> l1p[NB1], l2p[NB2];
+  if constexpr (SPLIT) {
+#pragma unroll
+    for (int q = 0; q < NB1; ++q) l1p[q] = pair_split<FORM>(l1f[q]);
+#pragma unroll
+    for (int q = 0; q < NB2; ++q) l2p[q] = pair_split<FORM>(l2f[q]);
+  }
 
   const auto xrs = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<void*>(a.X), 0, static_cast<int>(a.Il * a.m1 * a.m2 * a.Ir * sizeof(float)),
@@ -150,12 +204,23 @@ __device__ __forceinline__ void pair_run(const PairArgs& a, int64_t tile0, int64
         acc_t z[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) z[e] = acc_t{};
+        if constexpr (SPLIT) {
 #pragma unroll
-        for (int s = 0; s < 4; ++s)
+          for (int e = 0; e < 4; ++e) {
+            const FragT xv = {xr[4 * u + e][0], xr[4 * u + e][1], xr[4 * u + e][2],
+                              xr[4 * u + e][3]};
+            acc_t lo = acc_t{};
+            pair_mma<FORM>(l1p[q], pair_split<FORM>(xv), z[e], lo);
+            z[e] = z[e] + lo;
+          }
+        } else {
 #pragma unroll
-          for (int e = 0; e < 4; ++e)
-            z[e] = __builtin_amdgcn_mfma_f32_16x16x4f32(l1f[q][s], xr[4 * u + e][s], z[e], 0, 0,
-                                                        0);
+          for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+              z[e] = __builtin_amdgcn_mfma_f32_16x16x4f32(l1f[q][s], xr[4 * u + e][s], z[e], 0,
+                                                          0, 0);
+        }
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const f4v_t val = {z[0][v], z[1][v], z[2][v], z[3][v]};
@@ -172,11 +237,21 @@ __device__ __forceinline__ void pair_run(const PairArgs& a, int64_t tile0, int64
         acc_t y[NB2];
 #pragma unroll
         for (int q2 = 0; q2 < NB2; ++q2) y[q2] = acc_t{};
+        if constexpr (SPLIT) {
+          const PairPlanes<FORM> zp = pair_split<FORM>(zf);
 #pragma unroll
-        for (int s = 0; s < 4; ++s)
+          for (int q2 = 0; q2 < NB2; ++q2) {
+            acc_t lo = acc_t{};
+            pair_mma<FORM>(l2p[q2], zp, y[q2], lo);
+            y[q2] = y[q2] + lo;
+          }
+        } else {
 #pragma unroll
-          for (int q2 = 0; q2 < NB2; ++q2)
-            y[q2] = __builtin_amdgcn_mfma_f32_16x16x4f32(l2f[q2][s], zf[s], y[q2], 0, 0, 0);
+          for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int q2 = 0; q2 < NB2; ++q2)
+              y[q2] = __builtin_amdgcn_mfma_f32_16x16x4f32(l2f[q2][s], zf[s], y[q2], 0, 0, 0);
+        }
         const uint32_t i1 = 16 * q + il;
 #pragma unroll
         for (int q2 = 0; q2 < NB2; ++q2)
@@ -192,9 +267,18 @@ __device__ __forceinline__ void pair_run(const PairArgs& a, int64_t tile0, int64
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
   };
-  // workgroup tiles tile0, tile0 + tstep, ...; two register sets alternate so
-  // the next tile's X is in flight while the current one is computed
+  // workgroup tiles tile0, tile0 + tstep, ...; in FP32 two register sets
+  // alternate so the next tile's X is in flight while the current one is
+  // computed; the split forms (whose operand splits need the registers) load
+  // each tile's X before computing it
   int64_t tile = tile0;
+  if constexpr (SPLIT) {
+    for (; tile < ntiles; tile += tstep) {
+      load_x(tile, xa);
+      run(tile, xa);
+    }
+    return;
+  }
   if (tile < ntiles) load_x(tile, xa);
   while (tile < ntiles) {
     const int64_t nx = tile + tstep;

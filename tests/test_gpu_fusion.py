@@ -30,6 +30,35 @@ def kp():
     lib.kp_set_option(_lib.KP_OPT_FUSE, 1)
 
 
+@pytest.mark.parametrize("prec", ["bf16x3", "bf16x6"])
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_fused_split_forms_against_oracle(kp, case, prec):
+    """The BF16 split forms fuse pairs too: the fused chain within the form's
+    componentwise bound of the oracle, and within twice that bound of the
+    unfused chain (the fused pass takes the 16-long bf16 MFMA where the
+    unfused kernels zero-pad a 32-long one: equal up to rounding)."""
+    from paper_2112_11238_amd import _lib, tune
+    lib = _lib.load()
+    m, n = CASES[case]
+    T, Ls = kp_workloads.random_problem(6100 + case, m, n)
+    Td = to_dev(T, torch.float32)
+    Ld = [to_dev(L, torch.float32) for L in Ls]
+    launches = tune.products(Td, Ld, prec, which="launches")
+    assert any(p["kind"] == 2 for p in launches), launches
+    say("fusion", prec, m, n, [p["kind"] for p in launches])
+    S_f = kp.tucker(Td, Ld, prec=prec)
+    torch.cuda.synchronize()
+    assert lib.kp_set_option(_lib.KP_OPT_FUSE, 0) == 0
+    S_u = kp.tucker(Td, Ld, prec=prec)
+    torch.cuda.synchronize()
+    T64, L64 = cast64(T, torch.float32), [cast64(L, torch.float32) for L in Ls]
+    ref = oracle.tucker(T64, L64)
+    bound = chain_bound(T64, L64, prec, torch.float32)
+    got_f = S_f.double().cpu().numpy()
+    assert np.all(np.abs(got_f - ref) <= bound)
+    assert np.all(np.abs(got_f - S_u.double().cpu().numpy()) <= 2 * bound)
+
+
 @pytest.mark.parametrize("case", range(len(CASES)))
 def test_fused_equals_unfused_and_oracle(kp, case):
     from paper_2112_11238_amd import _lib, tune

@@ -280,10 +280,12 @@ def test_fusion_option_and_reported_launches(lib, L, tune):
         assert [p["kind"] == 2 for p in got6] == [False, False, True, True]
         assert [(p["Il"], p["m"], p["n"]) for p in got6 if p["kind"] == 2] == \
             [(24 * 24, 16, 24), (24 ** 4, 16, 24)]
-        # FP64 and the split forms are never fused
+        # FP64 is never fused; the split forms are, like FP32
         T64 = T.double()
         L64 = [x.double() for x in Ls]
         assert all(p["kind"] != 2 for p in tune.products(T64, L64, which="launches"))
-        assert all(p["kind"] != 2 for p in tune.products(T, Ls, "bf16x3", which="launches"))
+        for prec in ("bf16x3", "bf16x6"):
+            assert [p["kind"] == 2 for p in tune.products(T, Ls, prec, which="launches")] == \
+                [True, False, True]
     finally:
         lib.kp_set_option(L.KP_OPT_FUSE, 1)
