@@ -19,7 +19,7 @@ def kp():
 
 
 @pytest.mark.parametrize("n,scale", [(1, 0.5), (2, 3.0), (7, 0.01), (16, 1.0), (33, 20.0),
-                                     (64, 0.2), (100, 60.0), (256, 2.0)])
+                                     (64, 0.2), (100, 60.0), (200, 5.0), (256, 2.0)])
 def test_expm_matches_scipy(kp, n, scale):
     rng = np.random.default_rng(600 + n)
     A = rng.standard_normal((n, n)) * scale / np.sqrt(n)
@@ -30,6 +30,22 @@ def test_expm_matches_scipy(kp, n, scale):
     # both are backward-stable algorithms; the gap is bounded by the
     # conditioning of exp at A, small for these norms
     assert rel_max(E.cpu().numpy(), ref) < 1e-11
+
+
+def test_expm_many_squarings(kp):
+    # skew-symmetric, ||A||_1 in the thousands: s = ceil(log2(||A||_1 / theta_13))
+    # exceeds the squaring launches, so the last squarings run in the final
+    # launch; exp(A) is orthogonal, hence well conditioned
+    rng = np.random.default_rng(650)
+    n = 40
+    G = rng.standard_normal((n, n))
+    A = (G - G.T) * 100.0
+    norm1 = np.abs(A).sum(axis=0).max()
+    assert np.ceil(np.log2(norm1 / 5.371920351148152)) >= 10
+    say("expm skew", n, norm1)
+    E = kp.expm(to_dev(A, torch.float64), tau=1.0).cpu().numpy()
+    assert rel_max(E, scipy.linalg.expm(A)) < 1e-9
+    assert np.abs(E.T @ E - np.eye(n)).max() < 1e-9
 
 
 def test_expm_zero_and_identity_exact(kp):
