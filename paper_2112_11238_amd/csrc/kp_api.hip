@@ -155,6 +155,32 @@ void make_chain(const kp_tensor& T, const kp_matrix* const* L, bool definition_o
       if (active[k]) p->order[p->count++] = k;
   } else {
     plan_order(m, n, active, d, p->order, &p->count);
+    // FP32 data whose two leading modes fit a fused pair (m <= 16, n <= 32)
+    // and grow the tensor: when it costs no more flops, those modes go last,
+    // so that the pass writing the final (largest) tensor is the lead-layout
+    // pair, which reads and writes each fiber as one contiguous block. The
+    // order does not depend on whether fusion is enabled.
+    if (T.dtype == KP_F32 && d > 2 && active[0] && active[1] && n[0] * n[1] > m[0] * m[1] &&
+        pair_eligible(FORM_F32, 1, m[0], m[1], n[0], n[1])) {
+      auto flops = [&](const int* ord, int cnt) {
+        double size = 1.0, f = 0.0;
+        for (int k = 0; k < d; ++k) size *= static_cast<double>(m[k]);
+        for (int s = 0; s < cnt; ++s) {
+          const int k = ord[s];
+          f += 2.0 * static_cast<double>(n[k]) * size;
+          size = size / static_cast<double>(m[k]) * static_cast<double>(n[k]);
+        }
+        return f;
+      };
+      bool rest[KP_MAX_ORDER];
+      for (int k = 0; k < d; ++k) rest[k] = active[k] && k > 1;
+      int alt[KP_MAX_ORDER], cnt = 0;
+      plan_order(m, n, rest, d, alt, &cnt);
+      alt[cnt++] = 0;
+      alt[cnt++] = 1;
+      if (flops(alt, cnt) <= flops(p->order, p->count) * (1.0 + 1e-12))
+        for (int s = 0; s < cnt; ++s) p->order[s] = alt[s];
+    }
   }
   int64_t cur[KP_MAX_ORDER];
   for (int k = 0; k < d; ++k) cur[k] = m[k];
@@ -184,8 +210,9 @@ void chain_ws(const ChainPlan& p, size_t esize, size_t* off1, size_t* total) {
 }
 
 // Whether steps s and s + 1 of a chain without a cache run as one fused pass
-// (modes k and k + 1 in that order, both short, I_l > 1); fills the pass's
-// arguments except the tensors.
+// (modes k and k + 1 in that order, both short; the strided pair for
+// I_l > 1, the lead-layout pair for I_l = 1); fills the pass's arguments
+// except the tensors.
 bool fuse_step(const ChainPlan& p, int s, int d, const kp_matrix* const* L, int form,
                tile::PairArgs* pa) {
   if (!fusion_enabled() || tile_override() || s + 1 >= p.count) return false;

@@ -292,5 +292,189 @@ __device__ __forceinline__ void pair_run(const PairArgs& a, int64_t tile0, int64
   }
 }
 
+// Two consecutive mu-mode products on the two leading modes (I_l = 1):
+// fiber r, the index over the remaining modes, is the contiguous m1 x m2
+// block X[r; j1, j2] at r*m1*m2 + j1 + m1*j2, and its result the contiguous
+// n1 x n2 block Y[r; i1, i2] at r*n1*n2 + i1 + n1*i2.
+//   stage 1: Z(i1, j2) = sum_j1 L1(i1, j1) X(j1, j2), computed transposed
+//            (A = X: rows j2, k = j1; B = L1^T: k = j1, columns i1), so that
+//            each lane's result items (rows j2 = 4g + v, column i1 = c) are
+//            its own A operand of stage 2 (row i1 = c, k = j2 = 4g + v):
+//            Z never leaves the registers;
+//   stage 2: Y(i1, i2) = sum_j2 L2(i2, j2) Z(i1, j2) (A = Z, B = L2^T); each
+//            lane's result items are four consecutive i1 of one i2. They go
+//            through the wave's own LDS block (n1*n2 floats) and leave as
+//            lane-linear 16-byte stores: each store instruction writes 1 KB
+//            of contiguous output (storing the MFMA layout directly writes
+//            runs of 64 bytes, a slower pattern for HBM).
+// One wave per fiber at a time (its X block is one 16-byte load per lane
+// when m1 is a multiple of 4), no barrier; the waves of the grid take
+// consecutive fibers, so reads and writes stream through contiguous
+// memory. The k grouping of every product is that of the unfused kernels
+// (lane group g owns k = 4g .. 4g + 3 of a 16-long macro step), so in FP32
+// fused and unfused results are equal; the split forms use the 16-long
+// bf16 MFMA as the strided pair does.
+constexpr int kLeadLdsFloats = 32 * 32;  // per wave: one n1 x n2 output block
+
+template <int FORM, int NB1, int NB2>
+__device__ __forceinline__ void lead_pair_run(const PairArgs& a, int64_t wave0, int64_t wstep,
+                                              float* __restrict__ yw) {
+  using acc_t = f4_t;
+  typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+  constexpr bool SPLIT = FORM != FORM_F32;
+  const int lane = threadIdx.x & 63;
+  const int c = lane & 15;  // MFMA row (A) or column (B)
+  const int g = lane >> 4;  // lane group: k values 4g .. 4g + 3 of a macro step
+  // 32-bit index math: the host keeps every launch below 2^31 bytes
+  const uint32_t m1 = static_cast<uint32_t>(a.m1), m2 = static_cast<uint32_t>(a.m2);
+  const uint32_t n1 = static_cast<uint32_t>(a.n1), n2 = static_cast<uint32_t>(a.n2);
+  const int64_t F = a.Ir;
+  constexpr uint32_t kOut = 0x80000000u;  // >= any resource size here
+
+  // B operands, fixed for the kernel: L1^T (k = j1 = 4g + s, column
+  // i1 = 16 q + c) and L2^T (k = j2 = 4g + s, column i2 = 16 q + c), zero
+  // past n or m
+  f4v_t l1b[NB1], l2b[NB2];
+  const float* L1 = static_cast<const float*>(a.L1);
+  const float* L2 = static_cast<const float*>(a.L2);
+#pragma unroll
+  for (int q = 0; q < NB1; ++q)
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const uint32_t i = 16 * q + c, k = 4 * g + s;
+      l1b[q][s] = (i < n1 && k < m1) ? L1[i * a.rs1 + k * a.cs1] : 0.0f;
+    }
+#pragma unroll
+  for (int q = 0; q < NB2; ++q)
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const uint32_t i = 16 * q + c, k = 4 * g + s;
+      l2b[q][s] = (i < n2 && k < m2) ? L2[i * a.rs2 + k * a.cs2] : 0.0f;
+    }
+  PairPlanes<FORM> l1p[NB1], l2p[NB2];
+  if constexpr (SPLIT) {
+#pragma unroll
+    for (int q = 0; q < NB1; ++q) l1p[q] = pair_split<FORM>(l1b[q]);
+#pragma unroll
+    for (int q = 0; q < NB2; ++q) l2p[q] = pair_split<FORM>(l2b[q]);
+  }
+
+  const auto xrs = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<void*>(a.X), 0, static_cast<int>(F * a.m1 * a.m2 * sizeof(float)), kBufferFlags);
+  const auto yrs = __builtin_amdgcn_make_buffer_rsrc(
+      a.Y, 0, static_cast<int>(F * a.n1 * a.n2 * sizeof(float)), kBufferFlags);
+  const bool vin = (m1 & 3u) == 0, vout = (n1 & 3u) == 0;
+  const uint32_t nn = n1 * n2;             // floats per output block
+  const bool vstore = (nn & 3u) == 0;      // every block starts 16-byte aligned
+
+  // A operand of stage 1: X(j1 = 4g + s, j2 = c) of fiber r, zero past m
+  auto load = [&](int64_t r, f4v_t& x) {
+    const uint32_t base = static_cast<uint32_t>(r) * m1 * m2 * 4u;
+    if (vin) {
+      const uint32_t off = (4u * g < m1 && static_cast<uint32_t>(c) < m2)
+                               ? base + (4u * g + m1 * c) * 4u
+                               : kOut;
+      x = __builtin_bit_cast(f4v_t,
+                             __builtin_amdgcn_raw_buffer_load_b128(xrs, static_cast<int>(off), 0, 0));
+    } else {
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+        x[s] = buffer_load<float>(xrs, (4u * g + s < m1 && static_cast<uint32_t>(c) < m2)
+                                           ? base + (4u * g + s + m1 * c) * 4u
+                                           : kOut);
+    }
+  };
+  auto run = [&](int64_t r, const f4v_t& x) {
+    // stage 1: z[q] item v = Z(i1 = 16 q + c, j2 = 4g + v)
+    acc_t z[NB1];
+    if constexpr (SPLIT) {
+      const PairPlanes<FORM> xp = pair_split<FORM>(x);
+#pragma unroll
+      for (int q = 0; q < NB1; ++q) {
+        acc_t hi = acc_t{}, lo = acc_t{};
+        pair_mma<FORM>(xp, l1p[q], hi, lo);
+        z[q] = hi + lo;
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < NB1; ++q) {
+        z[q] = acc_t{};
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+          z[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(x[s], l1b[q][s], z[q], 0, 0, 0);
+      }
+    }
+    // stage 2 into the LDS block: y item v = Y(i1 = 16 q + 4g + v, i2 = 16 q2 + c)
+#pragma unroll
+    for (int q = 0; q < NB1; ++q) {
+      if (16u * q >= n1) break;
+      const f4v_t za = {z[q][0], z[q][1], z[q][2], z[q][3]};
+      PairPlanes<FORM> zp;
+      if constexpr (SPLIT) zp = pair_split<FORM>(za);
+#pragma unroll
+      for (int q2 = 0; q2 < NB2; ++q2) {
+        if (16u * q2 >= n2) break;
+        acc_t y;
+        if constexpr (SPLIT) {
+          acc_t lo = acc_t{};
+          y = acc_t{};
+          pair_mma<FORM>(zp, l2p[q2], y, lo);
+          y = y + lo;
+        } else {
+          y = acc_t{};
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            y = __builtin_amdgcn_mfma_f32_16x16x4f32(za[v], l2b[q2][v], y, 0, 0, 0);
+        }
+        const uint32_t i1 = 16 * q + 4 * g, i2 = 16 * q2 + c;
+        if (i2 < n2) {
+          if (vout) {
+            if (i1 < n1) *reinterpret_cast<f4v_t*>(yw + i1 + n1 * i2) = y;
+          } else {
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+              if (i1 + v < n1) yw[i1 + v + n1 * i2] = y[v];
+          }
+        }
+      }
+    }
+    // the wave's LDS writes above precede its reads below
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const uint32_t ybase = static_cast<uint32_t>(r) * nn * 4u;
+    if (vstore) {
+      for (uint32_t e = lane; e < nn / 4; e += 64) {
+        const f4v_t v = *reinterpret_cast<const f4v_t*>(yw + 4 * e);
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), yrs,
+                                               static_cast<int>(ybase + 16 * e), 0, 0);
+      }
+    } else {
+      for (uint32_t e = lane; e < nn; e += 64) buffer_store<float>(yw[e], yrs, ybase + 4 * e);
+    }
+    // the reads above precede the next fiber's writes
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  };
+  // fibers wave0, wave0 + wstep, ...: the X blocks of the next kLeadDepth
+  // fibers are in flight while one is computed (a wave's compute per fiber
+  // is short against the memory latency)
+  constexpr int kLeadDepth = 4;
+  f4v_t xb[kLeadDepth];
+#pragma unroll
+  for (int i = 0; i < kLeadDepth; ++i)
+    if (wave0 + i * wstep < F) load(wave0 + i * wstep, xb[i]);
+  for (int64_t r = wave0; r < F; r += kLeadDepth * wstep) {
+#pragma unroll
+    for (int i = 0; i < kLeadDepth; ++i) {
+      const int64_t ri = r + i * wstep;
+      if (ri >= F) break;
+      const f4v_t x = xb[i];
+      const int64_t rn = ri + kLeadDepth * wstep;
+      if (rn < F) load(rn, xb[i]);
+      run(ri, x);
+    }
+  }
+}
+
 }  // namespace tile
 }  // namespace kp

@@ -12,13 +12,22 @@ from gpu_util import cast64, chain_bound, say, to_dev
 pytestmark = pytest.mark.gpu
 
 CASES = [
-    # torch shapes m, n; at least one pair of consecutive short modes with I_l > 1
+    # torch shapes m, n; at least one pair of consecutive short modes (m <= 16,
+    # n <= 32) applied back to back: strided pairs (I_l > 1) and, where the
+    # two leading modes go last, the lead-layout pair (I_l = 1)
     ((6, 7, 16, 16, 16), (6, 7, 24, 24, 24)),
     ((5, 9, 13, 11, 7), (6, 10, 15, 14, 9)),
     ((3, 16, 16, 16, 16), (3, 24, 24, 24, 24)),
     ((40, 2, 3, 33), (41, 3, 4, 34)),
     ((30, 3, 5, 7), (31, 4, 6, 9)),
+    # lead-layout pairs: 16-byte loads and stores (m1, n1 multiples of 4) ...
+    ((3, 20, 9, 12), (3, 7, 9, 12)),
+    ((50, 16, 16), (20, 32, 24)),
+    # ... element loads and stores, three fibers (not a multiple of a workgroup)
+    ((30, 6, 13), (11, 6, 13)),
+    ((5, 4, 7), (3, 5, 9)),
 ]
+LEAD_CASES = [0, 2, 5, 6, 7, 8]  # cases whose chain has the lead-layout pair
 
 
 @pytest.fixture()
@@ -71,7 +80,9 @@ def test_fused_equals_unfused_and_oracle(kp, case):
         Ld[3] = Ld[3].t().contiguous().t()
     launches = tune.products(Td, Ld, which="launches")
     assert any(p["kind"] == 2 for p in launches), launches
-    say("fusion", m, n, [p["kind"] for p in launches])
+    if case in LEAD_CASES:
+        assert any(p["kind"] == 2 and p["Il"] == 1 for p in launches), launches
+    say("fusion", m, n, [(p["kind"], p["Il"]) for p in launches])
     S_f = kp.tucker(Td, Ld)
     torch.cuda.synchronize()
     assert lib.kp_set_option(_lib.KP_OPT_FUSE, 0) == 0
@@ -86,16 +97,16 @@ def test_fused_equals_unfused_and_oracle(kp, case):
 
 
 def test_fused_interp6d_full_size(kp):
-    """The 16^6 -> 24^6 interpolation: fused launches on the largest modes,
-    result equal to the unfused chain."""
+    """The 16^6 -> 24^6 interpolation: three fused passes, the last (writing
+    the 24^6 result) on the lead layout; result equal to the unfused chain."""
     from paper_2112_11238_amd import _lib, tune
     lib = _lib.load()
     T, Ls = kp_workloads.interp6d(seed=0)
     Td = to_dev(T, torch.float32)
     Ld = [to_dev(L, torch.float32) for L in Ls]
-    kinds = [p["kind"] for p in tune.products(Td, Ld, which="launches")]
-    say("fusion interp6d", kinds)
-    assert kinds.count(2) == 2
+    launches = tune.products(Td, Ld, which="launches")
+    say("fusion interp6d", [(p["kind"], p["Il"]) for p in launches])
+    assert [p["kind"] for p in launches] == [2, 2, 2] and launches[-1]["Il"] == 1
     S_f = kp.tucker(Td, Ld)
     torch.cuda.synchronize()
     lib.kp_set_option(_lib.KP_OPT_FUSE, 0)

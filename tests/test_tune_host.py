@@ -259,27 +259,45 @@ def test_fusion_option_and_reported_launches(lib, L, tune):
     assert lib.kp_set_option(L.KP_OPT_FUSE, 2) == -9
     assert lib.kp_set_option(99, 0) == -9 and lib.kp_get_option(99) == -9
     # canonical dims (16, 16, 16, 7, 6): the square modes go first (fewer
-    # flops), then modes 0, 1, 2; (3, 4) and (1, 2) are fusable pairs (I_l > 1,
-    # m <= 16, n <= 32), mode 0 (I_l = 1) runs alone
+    # flops), then mode 2, and the two leading modes last (same flops as any
+    # order of modes 0, 1, 2; FP32 data whose leading modes fit a pair):
+    # (3, 4) is a strided pair (I_l > 1, m <= 16, n <= 32), mode 2 runs
+    # alone, (0, 1) is the lead-layout pair (I_l = 1)
     T = torch.zeros((6, 7, 16, 16, 16), dtype=torch.float32)
     Ls = [torch.zeros((6, 6)), torch.zeros((7, 7))] + [torch.zeros((24, 16))] * 3
     try:
         got = tune.products(T, Ls, which="launches")
         assert [p["kind"] for p in got] == [2, 0, 2]   # FP32 m = 16 alone: k-loop tile
-        assert [(p["Il"], p["m"], p["n"]) for p in got] == [(4096, 7, 7), (1, 16, 24),
-                                                              (24, 16, 24)]
+        assert [(p["Il"], p["m"], p["n"]) for p in got] == [(4096, 7, 7), (256, 16, 24),
+                                                              (1, 16, 24)]
         assert lib.kp_set_option(L.KP_OPT_FUSE, 0) == 0
         assert all(p["kind"] != 2 for p in tune.products(T, Ls, which="launches"))
         assert len(tune.products(T, Ls, which="launches")) == 5
-        # six 16 -> 24 modes (the interpolation shape): pairs (2, 3) and (4, 5)
-        # of the 0-based steps move fewer elements than the first eligible
-        # pairs (1, 2), (3, 4) would (30.0 against 37.3 times 16^6)
+        # six 16 -> 24 modes (the interpolation shape): the leading modes go
+        # last, and the chain is three fused pairs, the last one on the lead
+        # layout
         assert lib.kp_set_option(L.KP_OPT_FUSE, 1) == 0
         T6 = torch.zeros((16,) * 6, dtype=torch.float32)
         got6 = tune.products(T6, [torch.zeros((24, 16))] * 6, which="launches")
-        assert [p["kind"] == 2 for p in got6] == [False, False, True, True]
-        assert [(p["Il"], p["m"], p["n"]) for p in got6 if p["kind"] == 2] == \
-            [(24 * 24, 16, 24), (24 ** 4, 16, 24)]
+        assert [p["kind"] == 2 for p in got6] == [True, True, True]
+        assert [(p["Il"], p["m"], p["n"]) for p in got6] == \
+            [(16 * 16, 16, 24), (16 * 16 * 24 * 24, 16, 24), (1, 16, 24)]
+        # unfused, the same order: six launches, the leading modes last
+        assert lib.kp_set_option(L.KP_OPT_FUSE, 0) == 0
+        got6u = tune.products(T6, [torch.zeros((24, 16))] * 6, which="launches")
+        assert [p["Il"] for p in got6u] == [256, 256 * 24, 256 * 576, 256 * 576 * 24, 1, 24]
+        assert lib.kp_set_option(L.KP_OPT_FUSE, 1) == 0
+        # FP64 keeps the minimum-flop order with its definition-order ties
+        order = (ctypes.c_int * 8)()
+        cnt = ctypes.c_int()
+        T6d = tensor(L, [16] * 6, dtype=0)
+        arr = mlist(L, [matrix(L, 24, 16, dtype=0) for _ in range(6)])
+        assert lib.kp_tucker_order(ctypes.byref(T6d), arr, order, ctypes.byref(cnt)) == 0
+        assert [order[k] for k in range(cnt.value)] == [1, 2, 3, 4, 5, 6]
+        T6f = tensor(L, [16] * 6, dtype=1)
+        arr = mlist(L, [matrix(L, 24, 16, dtype=1) for _ in range(6)])
+        assert lib.kp_tucker_order(ctypes.byref(T6f), arr, order, ctypes.byref(cnt)) == 0
+        assert [order[k] for k in range(cnt.value)] == [3, 4, 5, 6, 1, 2]
         # FP64 is never fused; the split forms are, like FP32
         T64 = T.double()
         L64 = [x.double() for x in Ls]
