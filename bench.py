@@ -134,13 +134,44 @@ def cpu_baseline(T, Ls, flops, budget_s=12.0):
 
 def traffic_probe(args):
     """Launches for a counter run: each FP64 mu-mode product of cube200 with
-    the default tiles, then a plain device-to-device copy of known size whose
-    counter readings calibrate the HBM byte counters."""
+    the default tiles (interp6d: the FP32 forward, fused, then unfused), then
+    a plain device-to-device copy of known size whose counter readings
+    calibrate the HBM byte counters."""
     import torch
 
     import paper_2112_11238_amd as kp
     dev = torch.device("cuda:0")
-    T, Ls = kp_workloads.cube200(seed=0)
+    if args.workload == "interp6d":
+        from paper_2112_11238_amd import _lib, tune
+        lib = _lib.load()
+        T, Ls = kp_workloads.interp6d(seed=0)
+        Td = torch.tensor(T, dtype=torch.float32, device=dev)
+        Lds = [torch.tensor(L, dtype=torch.float32, device=dev) for L in Ls]
+        plans = {}
+        for fuse in (1, 0):
+            lib.kp_set_option(_lib.KP_OPT_FUSE, fuse)
+            plans["fused" if fuse else "unfused"] = [
+                [p["kind"], p["Il"], p["m"], p["n"], p["Ir"]]
+                for p in tune.products(Td, Lds, which="launches")]
+            for _ in range(args.steps):
+                kp.tucker(Td, Lds)
+            torch.cuda.synchronize()
+        lib.kp_set_option(_lib.KP_OPT_FUSE, 1)
+        del Td
+    else:
+        T, Ls = kp_workloads.cube200(seed=0)
+    if args.workload == "interp6d":
+        copy_bytes = 512 << 20
+        a = torch.ones(copy_bytes // 8, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"probe": "traffic", "workload": "interp6d", "forwards": args.steps,
+                          "launches": plans, "input_bytes": 16 ** 6 * 4,
+                          "output_bytes": 24 ** 6 * 4, "copy_bytes_read": copy_bytes,
+                          "copy_bytes_written": copy_bytes, "copy_launches": 3}), flush=True)
+        return
     Td = torch.tensor(T, dtype=torch.float64, device=dev)
     Lds = [torch.tensor(L, dtype=torch.float64, device=dev) for L in Ls]
     out = torch.empty_like(Td)
