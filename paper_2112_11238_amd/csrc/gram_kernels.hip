@@ -87,6 +87,24 @@ __global__ __launch_bounds__(kThreads, 2) void gram_strip_kernel(GramArgs g, int
                                         lds);
 }
 
+// The fused backward step: the gram's partial tiles and Y = the mu-mode
+// product with L^T, from one read of Q (FP32, inner layout with 16-byte
+// fiber groups, n <= 32, m <= 32; JB = 16-row blocks of m, also the P tile's:
+// with m <= 16 the LDS footprint allows four workgroups per CU, whose
+// chunks in flight keep HBM busy).
+template <int JB>
+__global__ __launch_bounds__(kThreads, 2) void gram_product_kernel(GramArgs g, GramProduct prod,
+                                                                   int64_t chunks,
+                                                                   int64_t splits) {
+  constexpr int BR = strip_br<float>();
+  __shared__ __attribute__((aligned(16))) char lds[strip_lds_bytes<float, 2, JB, BR, JB>()];
+  const int64_t s = blockIdx.x;
+  const int64_t cb = s * chunks / splits, ce = (s + 1) * chunks / splits;
+  gram_strip<float, 2, JB, BR, true, true, JB>(g, cb, ce,
+                                               static_cast<float*>(g.part) + s * g.n * g.m, lds,
+                                               &prod);
+}
+
 using StripGramFn = void (*)(GramArgs, int64_t, int64_t);
 
 // vec: inner layout with fiber groups of 16 bytes (I_l a multiple of the
@@ -142,6 +160,48 @@ int strip_slots(StripGramFn fn) {
 }
 
 }  // namespace
+
+bool gram_product_eligible(int dtype, const void* Q, const void* P, const void* Y, int64_t Il,
+                           int64_t n, int64_t m, int64_t Ir) {
+  return dtype == KP_F32 && Il > 1 && Il % 4 == 0 && n >= 1 && m >= 1 && n <= 32 && m <= 32 &&
+         use_strip(Il, n, m, Ir, 4) && reinterpret_cast<uintptr_t>(Q) % 16 == 0 &&
+         reinterpret_cast<uintptr_t>(P) % 16 == 0 && reinterpret_cast<uintptr_t>(Y) % 16 == 0;
+}
+
+hipError_t launch_gram_product(const void* Q, const void* P, int64_t Il, int64_t n, int64_t m,
+                               int64_t Ir, void* part, void* dL, int64_t rs, int64_t cs,
+                               const kp_matrix& L, void* Y, hipStream_t stream) {
+  if (!gram_product_eligible(KP_F32, Q, P, Y, Il, n, m, Ir)) return hipErrorInvalidValue;
+  GramArgs g{};
+  g.Q = Q;
+  g.P = P;
+  g.part = part;
+  g.Il = Il;
+  g.n = n;
+  g.m = m;
+  g.Ir = Ir;
+  GramProduct prod{};
+  prod.L = static_cast<const float*>(L.data);
+  prod.Y = static_cast<float*>(Y);
+  prod.rs = L.rs;
+  prod.cs = L.cs;
+  const int64_t chunks = strip_chunks(Il, Ir, 4);
+  const StripGramFn probe = m <= 16 ? reinterpret_cast<StripGramFn>(gram_product_kernel<1>)
+                                    : reinterpret_cast<StripGramFn>(gram_product_kernel<2>);
+  int64_t splits = strip_slots(probe);
+  if (splits > chunks) splits = chunks;
+  if (splits > kMaxStripSplits) splits = kMaxStripSplits;
+  if (splits < 1) splits = 1;
+  if (m <= 16)
+    hipLaunchKernelGGL(gram_product_kernel<1>, dim3(static_cast<unsigned>(splits)),
+                       dim3(kThreads), 0, stream, g, prod, chunks, splits);
+  else
+    hipLaunchKernelGGL(gram_product_kernel<2>, dim3(static_cast<unsigned>(splits)),
+                       dim3(kThreads), 0, stream, g, prod, chunks, splits);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_reduce(KP_F32, part, splits, n, m, dL, rs, cs, stream);
+}
 
 int64_t gram_splits(int64_t Il, int64_t n, int64_t m, int64_t Ir) {
   const int64_t tiles = ((n + 63) / 64) * ((m + 63) / 64);

@@ -20,11 +20,29 @@ namespace kp {
 namespace gram {
 
 template <typename E, int NB, int MB, int BR>
+constexpr size_t strip_stage_bytes() {
+  return 2 * static_cast<size_t>(16 * (NB + MB)) * (BR + 16 / sizeof(E)) * sizeof(E);
+}
+// JB > 0: the fused variant's output staging (two buffers of 16*JB rows of
+// BR fibers) follows the operand staging
+template <typename E, int NB, int MB, int BR, int JB = 0>
 constexpr size_t strip_lds_bytes() {
-  constexpr size_t stage = 2 * static_cast<size_t>(16 * (NB + MB)) * (BR + 16 / sizeof(E)) * sizeof(E);
+  constexpr size_t stage = strip_stage_bytes<E, NB, MB, BR>() +
+                           2 * static_cast<size_t>(16 * JB) * BR * sizeof(E);
   constexpr size_t reduce = static_cast<size_t>(16 * NB) * (16 * MB) * sizeof(E);
   return stage > reduce ? stage : reduce;
 }
+
+// The fused backward step (gram_strip with JB > 0, FP32, inner layout with
+// 16-byte fiber groups): from the same staged chunks of Q, besides the
+// factor gradient's partial tile, the cotangent of the next mode down,
+// Y(r, j) = sum_i L(i, j) Q(r, i) (the mu-mode product with L^T, Y viewed
+// as (Il, m, Ir)), so Q is read from HBM once for both.
+struct GramProduct {
+  const float* L;  // n x m, L(i, j) = L[i*rs + j*cs]
+  float* Y;
+  int64_t rs, cs;
+};
 
 // Chunks [c_begin, c_end) of BR consecutive fibers; writes the partial n x m
 // tile to out[i*m + j]. At the end the waves' sums are added in LDS in
@@ -35,9 +53,16 @@ constexpr size_t strip_lds_bytes() {
 // (Il a multiple of KV, Q and P 16-byte aligned): a task is one row and KV
 // consecutive fibers, which are adjacent in memory, so it is one 16-byte
 // load and one 16-byte LDS store; lanes walk along the fiber groups.
-template <typename E, int NB, int MB, int BR, bool INNER, bool VEC = false>
+// JB > 0 (fused step): wave w also computes Y for fibers 16w .. 16w + 15 of
+// each chunk (MFMA rows = fibers, k = i in 16-long macro steps with lane
+// group g owning i = 4g .. 4g + 3, as in the unfused products; columns = j)
+// into an LDS block of 16*JB rows of BR fibers, and after the chunk's
+// barrier every thread stores 16 contiguous bytes of it (rows of BR fibers
+// leave as runs of 4*BR bytes).
+template <typename E, int NB, int MB, int BR, bool INNER, bool VEC = false, int JB = 0>
 __device__ __forceinline__ void gram_strip(const GramArgs& g, int64_t c_begin, int64_t c_end,
-                                           E* __restrict__ out, char* __restrict__ lds) {
+                                           E* __restrict__ out, char* __restrict__ lds,
+                                           const GramProduct* prod = nullptr) {
   using GT = GramT<E>;
   using frag = typename GT::frag;
   using acc_t = typename GT::acc_t;
@@ -56,6 +81,11 @@ __device__ __forceinline__ void gram_strip(const GramArgs& g, int64_t c_begin, i
   typedef E PTile[RP][LDR];
   QTile* sQ = reinterpret_cast<QTile*>(lds);
   PTile* sP = reinterpret_cast<PTile*>(lds + 2 * sizeof(QTile));
+  constexpr bool PROD = JB > 0;
+  static_assert(!PROD || (sizeof(E) == 4 && INNER && VEC && NB <= 2 && BR == 64),
+                "the fused step: FP32, inner layout with fiber groups, n <= 32, 64-fiber chunks");
+  typedef E OTile[16 * (JB > 0 ? JB : 1)][BR];
+  OTile* sO = reinterpret_cast<OTile*>(lds + strip_stage_bytes<E, NB, MB, BR>());
 
   // 32-bit index math: the host keeps each operand below 2^31 bytes
   const uint32_t Il = static_cast<uint32_t>(g.Il), n = static_cast<uint32_t>(g.n);
@@ -214,6 +244,60 @@ __device__ __forceinline__ void gram_strip(const GramArgs& g, int64_t c_begin, i
   // row blocks past n / column blocks past m hold no output: skip them
   const int nbu = static_cast<int>((n + 15) / 16), mbu = static_cast<int>((m + 15) / 16);
 
+  // fused step: B operands of the product, L(i = 16 h + 4 gq + s, j = 16 jb + c),
+  // zero past n or m; Y through a buffer resource (offsets past it dropped)
+  f4v_t lb[NB > 0 ? NB : 1][JB > 0 ? JB : 1];
+  const auto yrs = __builtin_amdgcn_make_buffer_rsrc(
+      PROD ? static_cast<void*>(prod->Y) : nullptr, 0,
+      PROD ? static_cast<int>(g.Il * g.m * g.Ir * sizeof(E)) : 0, tile::kBufferFlags);
+  if constexpr (PROD) {
+#pragma unroll
+    for (int h = 0; h < NB; ++h)
+#pragma unroll
+      for (int jb = 0; jb < JB; ++jb)
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+          const uint32_t i = 16 * h + 4 * gq + s4, j = 16 * jb + c;
+          lb[h][jb][s4] = (i < n && j < m) ? prod->L[i * prod->rs + j * prod->cs] : 0.0f;
+        }
+  }
+  // Y rows of this lane's fibers 16w + 4gq .. + 3 for chunk buffer `buf`
+  auto product = [&](int buf) {
+    f4_t o[JB > 0 ? JB : 1];
+#pragma unroll
+    for (int jb = 0; jb < JB; ++jb) o[jb] = f4_t{};
+#pragma unroll
+    for (int h = 0; h < NB; ++h) {
+      if (h >= nbu) break;
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) {
+        const E x = sQ[buf][16 * h + 4 * gq + s4][16 * w + c];
+#pragma unroll
+        for (int jb = 0; jb < JB; ++jb)
+          o[jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(x, lb[h][jb][s4], o[jb], 0, 0, 0);
+      }
+    }
+    // o[jb] item v: Y(fiber 16w + 4gq + v, j = 16 jb + c)
+#pragma unroll
+    for (int jb = 0; jb < JB; ++jb)
+      *reinterpret_cast<f4v_t*>(&sO[buf][16 * jb + c][16 * w + 4 * gq]) =
+          f4v_t{o[jb][0], o[jb][1], o[jb][2], o[jb][3]};
+  };
+  // every thread stores 16 contiguous bytes (4 fibers of one row j) per pass
+  auto store_y = [&](int buf, int64_t ch) {
+    const uint32_t r0 = static_cast<uint32_t>(ch) * BR;
+#pragma unroll
+    for (int e = t; e < 16 * JB * (BR / 4); e += kThreads) {
+      const uint32_t j = e / (BR / 4), r = r0 + 4 * (e % (BR / 4));
+      const uint32_t b = r / Il;
+      const uint32_t off = (r < F && j < m) ? ((r - b * Il) + Il * m * b + Il * j) * sizeof(E)
+                                           : kOut;
+      const f4v_t v = *reinterpret_cast<const f4v_t*>(&sO[buf][j][4 * (e % (BR / 4))]);
+      __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), yrs,
+                                             static_cast<int>(off), 0, 0);
+    }
+  };
+
   if (c_begin < c_end) {
     load(c_begin);
     store(0);
@@ -237,8 +321,10 @@ __device__ __forceinline__ void gram_strip(const GramArgs& g, int64_t c_begin, i
         for (int b = 0; b < MB; ++b)
           if (a < nbu && b < mbu) GT::step(fa[a], fb[b], acc[a][b]);
     }
+    if constexpr (PROD) product(buf);
     if (ch + 1 < c_end) store(buf ^ 1);
     __syncthreads();
+    if constexpr (PROD) store_y(buf, ch);
   }
 
   // wave sums added into one LDS tile in wave order

@@ -657,22 +657,35 @@ int kp_tucker_backward(const kp_tensor* G, const kp_tensor* T, const kp_matrix* 
   for (int k = 0; k < d; ++k) qdims[k] = L[k]->rows;
   for (int mu = d; mu >= 1 && mu >= last_needed; --mu) {
     const int k = mu - 1;
+    int64_t Il = 1, Ir = 1;
+    for (int j = 0; j < k; ++j) Il *= qdims[j];
+    for (int j = k + 1; j < d; ++j) Ir *= qdims[j];
+    const bool sweep = (mu > last_needed || (mu == 1 && dT)) && !(mu == 1 && !dT);
+    void* dst = sweep ? ((mu == 1) ? dT->data : wsb + b.q_off[(d - mu) & 1]) : nullptr;
+    // FP32 with both the factor gradient and the next cotangent needed, on a
+    // short mode: one pass over Q_mu computes both
+    if (dL && dL[k] && sweep && form == FORM_F32 && fusion_enabled() && !tile_override() &&
+        gram_product_eligible(T->dtype, Qmu, Pk[k], dst, Il, L[k]->rows, L[k]->cols, Ir)) {
+      st = hip_status(launch_gram_product(Qmu, Pk[k], Il, L[k]->rows, L[k]->cols, Ir,
+                                          wsb + b.g_off, dL[k]->data, dL[k]->rs, dL[k]->cs,
+                                          *L[k], dst, stream));
+      if (st) return st;
+      Qmu = dst;
+      qdims[k] = L[k]->cols;
+      continue;
+    }
     if (dL && dL[k]) {
-      int64_t Il = 1, Ir = 1;
-      for (int j = 0; j < k; ++j) Il *= qdims[j];
-      for (int j = k + 1; j < d; ++j) Ir *= qdims[j];
       st = hip_status(launch_gram(T->dtype, Qmu, Pk[k], Il, L[k]->rows, L[k]->cols, Ir,
                                   wsb + b.g_off, dL[k]->data, dL[k]->rs, dL[k]->cs, stream));
       if (st) return st;
     }
     if (mu == 1 && !dT) break;
-    if (mu > last_needed || (mu == 1 && dT)) {
+    if (sweep) {
       kp_matrix Lt = *L[k];
       Lt.rows = L[k]->cols;
       Lt.cols = L[k]->rows;
       Lt.rs = L[k]->cs;
       Lt.cs = L[k]->rs;
-      void* dst = (mu == 1) ? dT->data : wsb + b.q_off[(d - mu) & 1];
       const ModeArgs a = mode_args(Qmu, dst, qdims, d, k, Lt, 0);
       st = hip_status(launch_mode(form, a, tile_override(), stream));
       if (st) return st;

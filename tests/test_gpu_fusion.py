@@ -113,3 +113,37 @@ def test_fused_interp6d_full_size(kp):
     S_u = kp.tucker(Td, Ld)
     torch.cuda.synchronize()
     assert torch.equal(S_f, S_u)
+
+
+@pytest.mark.parametrize("m,n", [((16, 16, 16, 16), (24, 24, 24, 24)),
+                                 ((10, 12, 13), (12, 20, 28)),
+                                 ((4, 4, 4, 4, 4), (6, 6, 6, 6, 6))])
+def test_fused_backward_step(kp, m, n):
+    """FP32 backward: on short modes with I_l a multiple of 4 the factor
+    gradient and the next cotangent come from one pass over Q_mu. The
+    cotangent sweep (dT) equals the unfused one bitwise (same products, same
+    order); dL differs from it only in how the fiber sum is split, and both
+    meet the oracle within the chain bound."""
+    from paper_2112_11238_amd import _lib
+    from test_gpu_backward import grad_bounds
+    lib = _lib.load()
+    T, Ls = kp_workloads.random_problem(6200 + len(m), m, n)
+    G = np.random.default_rng(6300 + len(m)).standard_normal(n)
+    Td, Gd = to_dev(T, torch.float32), to_dev(G, torch.float32)
+    Ld = [to_dev(L, torch.float32) for L in Ls]
+    say("fused backward", m, n)
+    dT_f, dL_f = kp.tucker_backward(Gd, Td, Ld)
+    torch.cuda.synchronize()
+    assert lib.kp_set_option(_lib.KP_OPT_FUSE, 0) == 0
+    dT_u, dL_u = kp.tucker_backward(Gd, Td, Ld)
+    torch.cuda.synchronize()
+    assert torch.equal(dT_f, dT_u)
+    T64, G64 = cast64(T, torch.float32), cast64(G, torch.float32)
+    L64 = [cast64(L, torch.float32) for L in Ls]
+    rT, rL = oracle.tucker_vjp(T64, L64, G64)
+    bT, bL = grad_bounds(T64, L64, G64, "native", "f32")
+    assert np.all(np.abs(dT_f.double().cpu().numpy() - rT) <= bT)
+    for k in range(len(m)):
+        for got in (dL_f[k], dL_u[k]):
+            g = got.double().cpu().numpy()
+            assert np.all(np.abs(g - rL[k]) <= bL[k]), (k, float(np.max(np.abs(g - rL[k]) / bL[k])))
