@@ -97,7 +97,11 @@ __device__ __forceinline__ void gram_strip(const GramArgs& g, int64_t c_begin, i
   const int c = lane & 15;
   const int gq = lane >> 4;
 
-  E qv[NQ][KV], pv[NP][KV];
+  // two register sets (PF2): the loads of chunk ch + 2 are in flight while
+  // chunk ch is computed and chunk ch + 1 waits in the other set; the
+  // largest tiles (4 x 4 blocks) keep one set, the next chunk in flight
+  constexpr bool PF2 = !(NB == 4 && MB == 4);
+  E qv[PF2 ? 2 : 1][NQ][KV], pv[PF2 ? 2 : 1][NP][KV];
   // loads through buffer resources over Q and P (32-bit offsets); elements
   // past F, n or m get an offset past the resource and read as zero
   constexpr uint32_t kOut = 0x80000000u;
@@ -120,20 +124,21 @@ __device__ __forceinline__ void gram_strip(const GramArgs& g, int64_t c_begin, i
 #pragma unroll
     for (int e = 0; e < KV; ++e) dst[e] = f[e];
   };
-  auto load = [&](int64_t ch) {
+  auto load = [&](int64_t ch, auto set) {
+    constexpr int SET = decltype(set)::value;
     const uint32_t r0 = static_cast<uint32_t>(ch) * BR;
     if constexpr (GV) {
 #pragma unroll
       for (int s = 0; s < NQ; ++s) {
         const int id = t + s * kThreads;
         const uint32_t row = id / FG, r = r0 + (id % FG) * KV;
-        load_vec(qrs, r, id < TQ ? row : n, n, n, qv[s]);
+        load_vec(qrs, r, id < TQ ? row : n, n, n, qv[SET][s]);
       }
 #pragma unroll
       for (int s = 0; s < NP; ++s) {
         const int id = t + s * kThreads;
         const uint32_t row = id / FG, r = r0 + (id % FG) * KV;
-        load_vec(prs, r, id < TP ? row : m, m, m, pv[s]);
+        load_vec(prs, r, id < TP ? row : m, m, m, pv[SET][s]);
       }
       return;
     }
@@ -156,7 +161,7 @@ __device__ __forceinline__ void gram_strip(const GramArgs& g, int64_t c_begin, i
         const uint32_t i = row + (INNER ? e : 0);
         const bool ok = id < TQ && r < F && i < n;
         const uint32_t off = INNER ? base + Il * i : i + n * r;
-        qv[s][e] = tile::buffer_load<E>(qrs, ok ? off * sizeof(E) : kOut);
+        qv[SET][s][e] = tile::buffer_load<E>(qrs, ok ? off * sizeof(E) : kOut);
       }
     }
 #pragma unroll
@@ -176,11 +181,12 @@ __device__ __forceinline__ void gram_strip(const GramArgs& g, int64_t c_begin, i
         const uint32_t j = row + (INNER ? e : 0);
         const bool ok = id < TP && r < F && j < m;
         const uint32_t off = INNER ? base + Il * j : j + m * r;
-        pv[s][e] = tile::buffer_load<E>(prs, ok ? off * sizeof(E) : kOut);
+        pv[SET][s][e] = tile::buffer_load<E>(prs, ok ? off * sizeof(E) : kOut);
       }
     }
   };
-  auto store = [&](int buf) {
+  auto store = [&](int buf, auto set) {
+    constexpr int SET = decltype(set)::value;
     if constexpr (GV) {
 #pragma unroll
       for (int s = 0; s < NQ; ++s) {
@@ -188,7 +194,7 @@ __device__ __forceinline__ void gram_strip(const GramArgs& g, int64_t c_begin, i
         if (id >= TQ) continue;
         frag f;
 #pragma unroll
-        for (int e = 0; e < KV; ++e) f[e] = qv[s][e];
+        for (int e = 0; e < KV; ++e) f[e] = qv[SET][s][e];
         *reinterpret_cast<frag*>(&sQ[buf][id / FG][(id % FG) * KV]) = f;
       }
 #pragma unroll
@@ -197,7 +203,7 @@ __device__ __forceinline__ void gram_strip(const GramArgs& g, int64_t c_begin, i
         if (id >= TP) continue;
         frag f;
 #pragma unroll
-        for (int e = 0; e < KV; ++e) f[e] = pv[s][e];
+        for (int e = 0; e < KV; ++e) f[e] = pv[SET][s][e];
         *reinterpret_cast<frag*>(&sP[buf][id / FG][(id % FG) * KV]) = f;
       }
       return;
@@ -209,12 +215,12 @@ __device__ __forceinline__ void gram_strip(const GramArgs& g, int64_t c_begin, i
       if constexpr (INNER) {
         const int fr = id % BR, row = (id / BR) * KV;
 #pragma unroll
-        for (int e = 0; e < KV; ++e) sQ[buf][row + e][fr] = qv[s][e];
+        for (int e = 0; e < KV; ++e) sQ[buf][row + e][fr] = qv[SET][s][e];
       } else {
         const int fr = (id / RQ) * KV, row = id % RQ;
         frag f;
 #pragma unroll
-        for (int e = 0; e < KV; ++e) f[e] = qv[s][e];
+        for (int e = 0; e < KV; ++e) f[e] = qv[SET][s][e];
         *reinterpret_cast<frag*>(&sQ[buf][row][fr]) = f;
       }
     }
@@ -225,12 +231,12 @@ __device__ __forceinline__ void gram_strip(const GramArgs& g, int64_t c_begin, i
       if constexpr (INNER) {
         const int fr = id % BR, row = (id / BR) * KV;
 #pragma unroll
-        for (int e = 0; e < KV; ++e) sP[buf][row + e][fr] = pv[s][e];
+        for (int e = 0; e < KV; ++e) sP[buf][row + e][fr] = pv[SET][s][e];
       } else {
         const int fr = (id / RP) * KV, row = id % RP;
         frag f;
 #pragma unroll
-        for (int e = 0; e < KV; ++e) f[e] = pv[s][e];
+        for (int e = 0; e < KV; ++e) f[e] = pv[SET][s][e];
         *reinterpret_cast<frag*>(&sP[buf][row][fr]) = f;
       }
     }
@@ -298,14 +304,25 @@ __device__ __forceinline__ void gram_strip(const GramArgs& g, int64_t c_begin, i
     }
   };
 
+  using Set0 = std::integral_constant<int, 0>;
+  using Set1 = std::integral_constant<int, 1>;
   if (c_begin < c_end) {
-    load(c_begin);
-    store(0);
+    load(c_begin, Set0{});
+    if constexpr (PF2)
+      if (c_begin + 1 < c_end) load(c_begin + 1, Set1{});
+    store(0, Set0{});
   }
   __syncthreads();
   int buf = 0;
-  for (int64_t ch = c_begin; ch < c_end; ++ch, buf ^= 1) {
-    if (ch + 1 < c_end) load(ch + 1);
+  // chunk ch from LDS buffer `buf`. PF2: set CUR is free (its chunk is in
+  // LDS) and takes chunk ch + 2, set NXT holds chunk ch + 1; else the one
+  // set takes chunk ch + 1
+  auto step = [&](int64_t ch, auto cur, auto nxt) {
+    if constexpr (PF2) {
+      if (ch + 2 < c_end) load(ch + 2, cur);
+    } else {
+      if (ch + 1 < c_end) load(ch + 1, nxt);
+    }
 #pragma unroll
     for (int kk = w * KW; kk < (w + 1) * KW; kk += MK) {
       frag fa[NB], fb[MB];
@@ -322,9 +339,20 @@ __device__ __forceinline__ void gram_strip(const GramArgs& g, int64_t c_begin, i
           if (a < nbu && b < mbu) GT::step(fa[a], fb[b], acc[a][b]);
     }
     if constexpr (PROD) product(buf);
-    if (ch + 1 < c_end) store(buf ^ 1);
+    if (ch + 1 < c_end) store(buf ^ 1, nxt);
     __syncthreads();
     if constexpr (PROD) store_y(buf, ch);
+    buf ^= 1;
+  };
+  int64_t ch = c_begin;
+  if constexpr (PF2) {
+    for (; ch + 1 < c_end; ch += 2) {
+      step(ch, Set0{}, Set1{});
+      step(ch + 1, Set1{}, Set0{});
+    }
+    if (ch < c_end) step(ch, Set0{}, Set1{});
+  } else {
+    for (; ch < c_end; ++ch) step(ch, Set0{}, Set0{});
   }
 
   // wave sums added into one LDS tile in wave order
