@@ -108,7 +108,12 @@ __device__ __forceinline__ void strip_run(const ModeArgs& a, int64_t by, int64_t
     }
   }
 
-  G xr[XT][KV];
+  // BF16x6 (the most arithmetic per tile): two register sets, the loads of
+  // tile bx + 2 tstep in flight while tile bx is computed and tile
+  // bx + tstep waits in the other set; the other forms keep one set (the
+  // second one measured no faster, FP64 slower)
+  constexpr bool PF2 = FORM == FORM_BF16X6;
+  G xr[PF2 ? 2 : 1][XT][KV];
   // Global -> registers for fiber tile bx, through a buffer resource over
   // the launch's X (32-bit offsets, no per-load address arithmetic). Fibers
   // past F are clamped to the last one (their outputs are never stored); a
@@ -118,7 +123,8 @@ __device__ __forceinline__ void strip_run(const ModeArgs& a, int64_t by, int64_t
       const_cast<void*>(a.X), 0, static_cast<int>(a.Il * a.m * a.Ir * sizeof(G)), kBufferFlags);
   const auto yrs = __builtin_amdgcn_make_buffer_rsrc(
       a.Y, 0, static_cast<int>(a.Il * a.n * a.Ir * sizeof(G)), kBufferFlags);
-  auto load_x = [&](int64_t bx) {
+  auto load_x = [&](int64_t bx, auto set) {
+    constexpr int SET = decltype(set)::value;
     const uint32_t f0 = static_cast<uint32_t>(bx) * BF;
 #pragma unroll
     for (int s = 0; s < XT; ++s) {
@@ -144,19 +150,20 @@ __device__ __forceinline__ void strip_run(const ModeArgs& a, int64_t by, int64_t
           const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(xrs, static_cast<int>(off), 0, 0);
           const g16 gv = __builtin_bit_cast(g16, v);
 #pragma unroll
-          for (int e = 0; e < PER; ++e) xr[s][q * PER + e] = gv[e];
+          for (int e = 0; e < PER; ++e) xr[SET][s][q * PER + e] = gv[e];
         }
       } else {
         const uint32_t ks = INNER ? Il : 1;
 #pragma unroll
         for (int e = 0; e < KV; ++e) {
           const uint32_t k = kb + e;
-          xr[s][e] = buffer_load<G>(xrs, k < m ? (base + k * ks) * sizeof(G) : kOut);
+          xr[SET][s][e] = buffer_load<G>(xrs, k < m ? (base + k * ks) * sizeof(G) : kOut);
         }
       }
     }
   };
-  auto store_x = [&](int buf) {
+  auto store_x = [&](int buf, auto set) {
+    constexpr int SET = decltype(set)::value;
 #pragma unroll
     for (int s = 0; s < XT; ++s) {
       const int id = t + s * kThreads;
@@ -164,28 +171,39 @@ __device__ __forceinline__ void strip_run(const ModeArgs& a, int64_t by, int64_t
       const int row = xrow[s], kg = xkg[s];
       if constexpr (SPLIT) {
         bf16x8_t pl[P];
-        split_bf16_group<P, KV>(xr[s], pl);
+        split_bf16_group<P, KV>(xr[SET][s], pl);
 #pragma unroll
         for (int p = 0; p < P; ++p)
           *reinterpret_cast<bf16x8_t*>(&sX[buf][p][row][kg * KV]) = pl[p];
       } else {
         FragT f;
 #pragma unroll
-        for (int e = 0; e < KV; ++e) f[e] = xr[s][e];
+        for (int e = 0; e < KV; ++e) f[e] = xr[SET][s][e];
         *reinterpret_cast<FragT*>(&sX[buf][0][row][kg * KV]) = f;
       }
     }
   };
 
+  using Set0 = std::integral_constant<int, 0>;
+  using Set1 = std::integral_constant<int, 1>;
   if (t0 < ntiles) {
-    load_x(t0);
-    store_x(0);
+    load_x(t0, Set0{});
+    if constexpr (PF2)
+      if (t0 + tstep < ntiles) load_x(t0 + tstep, Set1{});
+    store_x(0, Set0{});
   }
   __syncthreads();
   int buf = 0;
-  for (int64_t bx = t0; bx < ntiles; bx += tstep, buf ^= 1) {
+  // tile bx from LDS buffer `buf`. PF2: set CUR is free (its tile is in
+  // LDS) and takes tile bx + 2 tstep, set NXT holds tile bx + tstep; else
+  // the one set takes tile bx + tstep
+  auto step = [&](int64_t bx, auto cur, auto nxt) {
     const int64_t nx = bx + tstep;
-    if (nx < ntiles) load_x(nx);
+    if constexpr (PF2) {
+      if (nx + tstep < ntiles) load_x(nx + tstep, cur);
+    } else {
+      if (nx < ntiles) load_x(nx, nxt);
+    }
     acc_t hi[QB][PB], lo[QB][PB];
 #pragma unroll
     for (int q = 0; q < QB; ++q)
@@ -241,8 +259,19 @@ __device__ __forceinline__ void strip_run(const ModeArgs& a, int64_t by, int64_t
           store_out<INNER, G>(val[v], yrs, off, a.accumulate, c);
         }
       }
-    if (nx < ntiles) store_x(buf ^ 1);
+    if (nx < ntiles) store_x(buf ^ 1, nxt);
     __syncthreads();
+    buf ^= 1;
+  };
+  int64_t bx = t0;
+  if constexpr (PF2) {
+    for (; bx + tstep < ntiles; bx += 2 * tstep) {
+      step(bx, Set0{}, Set1{});
+      step(bx + tstep, Set1{}, Set0{});
+    }
+    if (bx < ntiles) step(bx, Set0{}, Set1{});
+  } else {
+    for (; bx < ntiles; bx += tstep) step(bx, Set0{}, Set0{});
   }
 }
 
