@@ -92,7 +92,7 @@ __global__ __launch_bounds__(kThreads, 2) void gram_strip_kernel(GramArgs g, int
 // fiber groups, n <= 32, m <= 32; JB = 16-row blocks of m, also the P tile's:
 // with m <= 16 the LDS footprint allows four workgroups per CU, whose
 // chunks in flight keep HBM busy).
-template <int JB>
+template <int PFORM, int JB>
 __global__ __launch_bounds__(kThreads, 2) void gram_product_kernel(GramArgs g, GramProduct prod,
                                                                    int64_t chunks,
                                                                    int64_t splits) {
@@ -100,9 +100,8 @@ __global__ __launch_bounds__(kThreads, 2) void gram_product_kernel(GramArgs g, G
   __shared__ __attribute__((aligned(16))) char lds[strip_lds_bytes<float, 2, JB, BR, JB>()];
   const int64_t s = blockIdx.x;
   const int64_t cb = s * chunks / splits, ce = (s + 1) * chunks / splits;
-  gram_strip<float, 2, JB, BR, true, true, JB>(g, cb, ce,
-                                               static_cast<float*>(g.part) + s * g.n * g.m, lds,
-                                               &prod);
+  gram_strip<float, 2, JB, BR, true, true, JB, PFORM>(
+      g, cb, ce, static_cast<float*>(g.part) + s * g.n * g.m, lds, &prod);
 }
 
 using StripGramFn = void (*)(GramArgs, int64_t, int64_t);
@@ -168,9 +167,10 @@ bool gram_product_eligible(int dtype, const void* Q, const void* P, const void* 
          reinterpret_cast<uintptr_t>(P) % 16 == 0 && reinterpret_cast<uintptr_t>(Y) % 16 == 0;
 }
 
-hipError_t launch_gram_product(const void* Q, const void* P, int64_t Il, int64_t n, int64_t m,
-                               int64_t Ir, void* part, void* dL, int64_t rs, int64_t cs,
+hipError_t launch_gram_product(int form, const void* Q, const void* P, int64_t Il, int64_t n,
+                               int64_t m, int64_t Ir, void* part, void* dL, int64_t rs, int64_t cs,
                                const kp_matrix& L, void* Y, hipStream_t stream) {
+  if (form != FORM_F32 && form != FORM_BF16X3 && form != FORM_BF16X6) return hipErrorInvalidValue;
   if (!gram_product_eligible(KP_F32, Q, P, Y, Il, n, m, Ir)) return hipErrorInvalidValue;
   GramArgs g{};
   g.Q = Q;
@@ -186,18 +186,19 @@ hipError_t launch_gram_product(const void* Q, const void* P, int64_t Il, int64_t
   prod.rs = L.rs;
   prod.cs = L.cs;
   const int64_t chunks = strip_chunks(Il, Ir, 4);
-  const StripGramFn probe = m <= 16 ? reinterpret_cast<StripGramFn>(gram_product_kernel<1>)
-                                    : reinterpret_cast<StripGramFn>(gram_product_kernel<2>);
-  int64_t splits = strip_slots(probe);
+  using Fn = void (*)(GramArgs, GramProduct, int64_t, int64_t);
+  const Fn fn = form == FORM_F32      ? (m <= 16 ? gram_product_kernel<FORM_F32, 1>
+                                                 : gram_product_kernel<FORM_F32, 2>)
+                : form == FORM_BF16X3 ? (m <= 16 ? gram_product_kernel<FORM_BF16X3, 1>
+                                                 : gram_product_kernel<FORM_BF16X3, 2>)
+                                      : (m <= 16 ? gram_product_kernel<FORM_BF16X6, 1>
+                                                 : gram_product_kernel<FORM_BF16X6, 2>);
+  int64_t splits = strip_slots(reinterpret_cast<StripGramFn>(fn));
   if (splits > chunks) splits = chunks;
   if (splits > kMaxStripSplits) splits = kMaxStripSplits;
   if (splits < 1) splits = 1;
-  if (m <= 16)
-    hipLaunchKernelGGL(gram_product_kernel<1>, dim3(static_cast<unsigned>(splits)),
-                       dim3(kThreads), 0, stream, g, prod, chunks, splits);
-  else
-    hipLaunchKernelGGL(gram_product_kernel<2>, dim3(static_cast<unsigned>(splits)),
-                       dim3(kThreads), 0, stream, g, prod, chunks, splits);
+  hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>(splits)), dim3(kThreads), 0, stream, g, prod,
+                     chunks, splits);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return launch_reduce(KP_F32, part, splits, n, m, dL, rs, cs, stream);

@@ -15,6 +15,7 @@
 
 #include "gram_tile.h"
 #include "mode_tile.h"
+#include "pair_tile.h"
 
 namespace kp {
 namespace gram {
@@ -58,8 +59,11 @@ struct GramProduct {
 // group g owning i = 4g .. 4g + 3, as in the unfused products; columns = j)
 // into an LDS block of 16*JB rows of BR fibers, and after the chunk's
 // barrier every thread stores 16 contiguous bytes of it (rows of BR fibers
-// leave as runs of 4*BR bytes).
-template <typename E, int NB, int MB, int BR, bool INNER, bool VEC = false, int JB = 0>
+// leave as runs of 4*BR bytes). PFORM: the product's form, FP32 MFMA or a
+// BF16 split form (16-long bf16 MFMAs on the operands' planes, the leading
+// product in one accumulator, the corrections in another).
+template <typename E, int NB, int MB, int BR, bool INNER, bool VEC = false, int JB = 0,
+          int PFORM = FORM_F32>
 __device__ __forceinline__ void gram_strip(const GramArgs& g, int64_t c_begin, int64_t c_end,
                                            E* __restrict__ out, char* __restrict__ lds,
                                            const GramProduct* prod = nullptr) {
@@ -253,6 +257,8 @@ __device__ __forceinline__ void gram_strip(const GramArgs& g, int64_t c_begin, i
   // fused step: B operands of the product, L(i = 16 h + 4 gq + s, j = 16 jb + c),
   // zero past n or m; Y through a buffer resource (offsets past it dropped)
   f4v_t lb[NB > 0 ? NB : 1][JB > 0 ? JB : 1];
+  constexpr bool PSPLIT = PFORM != FORM_F32;
+  tile::PairPlanes<PSPLIT ? PFORM : FORM_BF16X3> lp[PSPLIT ? NB : 1][PSPLIT ? JB : 1];
   const auto yrs = __builtin_amdgcn_make_buffer_rsrc(
       PROD ? static_cast<void*>(prod->Y) : nullptr, 0,
       PROD ? static_cast<int>(g.Il * g.m * g.Ir * sizeof(E)) : 0, tile::kBufferFlags);
@@ -266,21 +272,45 @@ __device__ __forceinline__ void gram_strip(const GramArgs& g, int64_t c_begin, i
           const uint32_t i = 16 * h + 4 * gq + s4, j = 16 * jb + c;
           lb[h][jb][s4] = (i < n && j < m) ? prod->L[i * prod->rs + j * prod->cs] : 0.0f;
         }
+    if constexpr (PSPLIT) {
+#pragma unroll
+      for (int h = 0; h < NB; ++h)
+#pragma unroll
+        for (int jb = 0; jb < JB; ++jb) lp[h][jb] = tile::pair_split<PFORM>(lb[h][jb]);
+    }
   }
   // Y rows of this lane's fibers 16w + 4gq .. + 3 for chunk buffer `buf`
   auto product = [&](int buf) {
     f4_t o[JB > 0 ? JB : 1];
 #pragma unroll
     for (int jb = 0; jb < JB; ++jb) o[jb] = f4_t{};
+    if constexpr (PSPLIT) {
+      f4_t lo[JB > 0 ? JB : 1];
 #pragma unroll
-    for (int h = 0; h < NB; ++h) {
-      if (h >= nbu) break;
+      for (int jb = 0; jb < JB; ++jb) lo[jb] = f4_t{};
 #pragma unroll
-      for (int s4 = 0; s4 < 4; ++s4) {
-        const E x = sQ[buf][16 * h + 4 * gq + s4][16 * w + c];
+      for (int h = 0; h < NB; ++h) {
+        if (h >= nbu) break;
+        f4v_t xv;
 #pragma unroll
-        for (int jb = 0; jb < JB; ++jb)
-          o[jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(x, lb[h][jb][s4], o[jb], 0, 0, 0);
+        for (int s4 = 0; s4 < 4; ++s4) xv[s4] = sQ[buf][16 * h + 4 * gq + s4][16 * w + c];
+        const auto xp = tile::pair_split<PFORM>(xv);
+#pragma unroll
+        for (int jb = 0; jb < JB; ++jb) tile::pair_mma<PFORM>(xp, lp[h][jb], o[jb], lo[jb]);
+      }
+#pragma unroll
+      for (int jb = 0; jb < JB; ++jb) o[jb] = o[jb] + lo[jb];
+    } else {
+#pragma unroll
+      for (int h = 0; h < NB; ++h) {
+        if (h >= nbu) break;
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+          const E x = sQ[buf][16 * h + 4 * gq + s4][16 * w + c];
+#pragma unroll
+          for (int jb = 0; jb < JB; ++jb)
+            o[jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(x, lb[h][jb][s4], o[jb], 0, 0, 0);
+        }
       }
     }
     // o[jb] item v: Y(fiber 16w + 4gq + v, j = 16 jb + c)

@@ -662,11 +662,11 @@ int kp_tucker_backward(const kp_tensor* G, const kp_tensor* T, const kp_matrix* 
     for (int j = k + 1; j < d; ++j) Ir *= qdims[j];
     const bool sweep = (mu > last_needed || (mu == 1 && dT)) && !(mu == 1 && !dT);
     void* dst = sweep ? ((mu == 1) ? dT->data : wsb + b.q_off[(d - mu) & 1]) : nullptr;
-    // FP32 with both the factor gradient and the next cotangent needed, on a
-    // short mode: one pass over Q_mu computes both
-    if (dL && dL[k] && sweep && form == FORM_F32 && fusion_enabled() && !tile_override() &&
+    // FP32 data with both the factor gradient and the next cotangent needed,
+    // on a short mode: one pass over Q_mu computes both
+    if (dL && dL[k] && sweep && form != FORM_F64 && fusion_enabled() && !tile_override() &&
         gram_product_eligible(T->dtype, Qmu, Pk[k], dst, Il, L[k]->rows, L[k]->cols, Ir)) {
-      st = hip_status(launch_gram_product(Qmu, Pk[k], Il, L[k]->rows, L[k]->cols, Ir,
+      st = hip_status(launch_gram_product(form, Qmu, Pk[k], Il, L[k]->rows, L[k]->cols, Ir,
                                           wsb + b.g_off, dL[k]->data, dL[k]->rs, dL[k]->cs,
                                           *L[k], dst, stream));
       if (st) return st;

@@ -36,12 +36,13 @@ hipError_t launch_gram(int dtype, const void* Q, const void* P, int64_t Il, int6
                        int64_t Ir, void* part, void* dL, int64_t rs, int64_t cs,
                        hipStream_t stream);
 // The same contraction fused with Y = Q x_mu L^T (L: n x m, Y viewed as
-// (Il, m, Ir)), reading Q once: FP32, Il a multiple of 4, n, m <= 32, Q, P and
-// Y 16-byte aligned (gram_product_eligible); same `part` workspace.
+// (Il, m, Ir)), reading Q once: FP32 data, Il a multiple of 4, n, m <= 32, Q,
+// P and Y 16-byte aligned (gram_product_eligible); the product in `form`
+// (FP32 or a BF16 split form), the gradient in FP32; same `part` workspace.
 bool gram_product_eligible(int dtype, const void* Q, const void* P, const void* Y, int64_t Il,
                            int64_t n, int64_t m, int64_t Ir);
-hipError_t launch_gram_product(const void* Q, const void* P, int64_t Il, int64_t n, int64_t m,
-                               int64_t Ir, void* part, void* dL, int64_t rs, int64_t cs,
+hipError_t launch_gram_product(int form, const void* Q, const void* P, int64_t Il, int64_t n,
+                               int64_t m, int64_t Ir, void* part, void* dL, int64_t rs, int64_t cs,
                                const kp_matrix& L, void* Y, hipStream_t stream);
 
 }  // namespace kp

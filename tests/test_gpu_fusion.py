@@ -147,3 +147,36 @@ def test_fused_backward_step(kp, m, n):
         for got in (dL_f[k], dL_u[k]):
             g = got.double().cpu().numpy()
             assert np.all(np.abs(g - rL[k]) <= bL[k]), (k, float(np.max(np.abs(g - rL[k]) / bL[k])))
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "bf16x6"])
+@pytest.mark.parametrize("m,n", [((16, 16, 16, 16), (24, 24, 24, 24)),
+                                 ((10, 12, 13), (12, 20, 28))])
+def test_fused_backward_step_split_forms(kp, m, n, prec):
+    """The fused backward step in the BF16 split forms: the product takes the
+    16-long bf16 MFMA where the unfused kernels zero-pad a 32-long one, so dT
+    agrees with the unfused sweep to rounding; both sweeps and every factor
+    gradient meet the oracle within the form's chain bound."""
+    from paper_2112_11238_amd import _lib
+    from test_gpu_backward import grad_bounds
+    lib = _lib.load()
+    T, Ls = kp_workloads.random_problem(6400 + len(m), m, n)
+    G = np.random.default_rng(6500 + len(m)).standard_normal(n)
+    Td, Gd = to_dev(T, torch.float32), to_dev(G, torch.float32)
+    Ld = [to_dev(L, torch.float32) for L in Ls]
+    say("fused backward", prec, m, n)
+    dT_f, dL_f = kp.tucker_backward(Gd, Td, Ld, prec)
+    torch.cuda.synchronize()
+    assert lib.kp_set_option(_lib.KP_OPT_FUSE, 0) == 0
+    dT_u, dL_u = kp.tucker_backward(Gd, Td, Ld, prec)
+    torch.cuda.synchronize()
+    T64, G64 = cast64(T, torch.float32), cast64(G, torch.float32)
+    L64 = [cast64(L, torch.float32) for L in Ls]
+    rT, rL = oracle.tucker_vjp(T64, L64, G64)
+    bT, bL = grad_bounds(T64, L64, G64, prec, "f32")
+    for got in (dT_f, dT_u):
+        assert np.all(np.abs(got.double().cpu().numpy() - rT) <= bT)
+    for k in range(len(m)):
+        for got in (dL_f[k], dL_u[k]):
+            g = got.double().cpu().numpy()
+            assert np.all(np.abs(g - rL[k]) <= bL[k]), (k, float(np.max(np.abs(g - rL[k]) / bL[k])))
