@@ -370,7 +370,12 @@ int kp_semilinear_imex_f64(kp_tensor* U, const double* const* lower, const doubl
  *           distance in k-chunks (1 or 2; 0: 1);
  *   kind 1  strip tile for short contractions (m <= bk): the workgroup keeps
  *           its nb blocks of L rows in LDS and streams many fiber tiles of
- *           64*fb fibers; bk is the padded contraction length, occ = pf = 0.
+ *           64*fb fibers; bk is the padded contraction length, occ = pf = 0;
+ *   kind 3  wide tile of the BF16 split forms: the 4 waves split 64*nb rows
+ *           of n (nb 16-wide blocks each), each loading and splitting its
+ *           own rows of L, and share 16*fb fibers staged in LDS; bk = 32,
+ *           pf = 2 (two chunks of fibers in flight).
+ * Kind 2 is not a tile: it names a fused pair of modes in launch reports.
  * kp_force_tile forces the tile of every later mode-product launch in this
  * process; nb <= 0 restores the table / default choice. KP_ERR_VALUE for a
  * negative or out-of-range field. A launch whose forced tile is not a

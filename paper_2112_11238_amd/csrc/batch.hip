@@ -309,6 +309,8 @@ struct Plan {
 // has it, else the executor's variant with the closest n coverage.
 int pick_batch_variant(int form, const ModeArgs& a) {
   const ModeTile want = default_mode_tile(form, a, false);
+  // n blocks per workgroup of the wanted tile (a wide tile has 4 waves of nb)
+  const int want_nb = want.kind == 3 ? 4 * want.nb : want.nb;
   int nv;
   const BVar* vs = host_vars(form, &nv);
   int best = 0;
@@ -322,7 +324,7 @@ int pick_batch_variant(int form, const ModeArgs& a) {
     // padding waste of n, then prefer larger fiber tiles for small n
     const int64_t bn = 16 * vs[i].nb;
     const int64_t padded = ((a.n + bn - 1) / bn) * bn;
-    const int64_t cost = (padded - a.n) * 8 + (vs[i].nb == want.nb ? 0 : 1);
+    const int64_t cost = (padded - a.n) * 8 + (vs[i].nb == want_nb ? 0 : 1);
     if (best_cost < 0 || cost < best_cost) {
       best_cost = cost;
       best = i;

@@ -94,7 +94,9 @@ extern "C" int kp_force_tile(int nb, int fb, int bk, int occ, int pf, int kind) 
     kp::g_force = false;
     return KP_OK;
   }
-  if (fb <= 0 || bk <= 0 || occ < 0 || pf < 0 || pf > 2 || kind < 0 || kind > 1)
+  // kinds: 0 k-loop tile, 1 strip tile, 3 wide tile (2 names a fused pair in
+  // launch reports and is not a tile)
+  if (fb <= 0 || bk <= 0 || occ < 0 || pf < 0 || pf > 2 || kind < 0 || kind > 3 || kind == 2)
     return KP_ERR_VALUE;
   kp::g_forced.kind = kind;
   kp::g_forced.nb = nb;
@@ -124,7 +126,7 @@ extern "C" int kp_tune_set(const kp_tune_entry* e) {
   if (!e) return KP_ERR_NULL;
   if (!kp::valid_key(e->form, e->Il, e->m, e->n, e->Ir)) return KP_ERR_VALUE;
   if (e->nb <= 0 || e->fb <= 0 || e->bk <= 0 || e->occ < 0 || e->pf < 0 || e->pf > 2 ||
-      e->kind < 0 || e->kind > 1)
+      e->kind < 0 || e->kind > 3 || e->kind == 2)
     return KP_ERR_VALUE;
   kp::ModeTile t{e->nb, e->fb, e->bk, e->occ, e->pf, e->kind};
   kp::ModeTile r;

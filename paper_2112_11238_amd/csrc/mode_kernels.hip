@@ -23,6 +23,7 @@
 // its own accumulator and all correction products in a second one.
 #include "kp_common.h"
 #include "mode_tile.h"
+#include "wide_tile.h"
 
 namespace kp {
 namespace {
@@ -53,6 +54,18 @@ __global__ __launch_bounds__(kThreads, OCC) void mode_kernel(ModeArgs a, int64_t
   int64_t bx, by;
   xcd_tile(gx, gy, &bx, &by);
   mode_tile<FORM, NB, FB, BK, INNER, PF, VEC>(a, bx, by, lds);
+}
+
+// Wide tiles of the BF16 split forms (wide_tile.h): the four waves split the
+// n rows (NBW 16-row blocks each) and share FBW 16-fiber blocks; 32-wide k
+// steps.
+template <int FORM, int NBW, int FBW, int OCC, bool INNER, bool VEC>
+__global__ __launch_bounds__(kThreads, OCC) void wide_kernel(ModeArgs a, int64_t gx,
+                                                             int64_t gy) {
+  __shared__ __attribute__((aligned(16))) char lds[wide_lds_bytes<FORM, FBW, 4, 32>()];
+  int64_t bx, by;
+  xcd_tile(gx, gy, &bx, &by);
+  wide_tile<FORM, NBW, FBW, 4, 32, INNER, VEC>(a, bx, by, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -100,6 +113,29 @@ const Variant kVariants[] = {
     KP_VP(FORM_BF16X6, 4, 1, 32, 2, 2),
 };
 
+// Wide tiles (kind 3): nb = NBW, fb = FBW, bk = 32, pf = 2 (two chunks of
+// fibers in flight).
+#define KP_W(FORM, NBW, FBW, OCC)                                                   \
+  {FORM, NBW, FBW, 32, OCC, 2,                                                      \
+   {{wide_kernel<FORM, NBW, FBW, OCC, false, false>,                                \
+     wide_kernel<FORM, NBW, FBW, OCC, false, true>},                                \
+    {wide_kernel<FORM, NBW, FBW, OCC, true, false>,                                 \
+     wide_kernel<FORM, NBW, FBW, OCC, true, true>}}}
+
+const Variant kWide[] = {
+    KP_W(FORM_BF16X3, 2, 4, 2), KP_W(FORM_BF16X3, 4, 2, 2), KP_W(FORM_BF16X3, 4, 4, 1),
+    KP_W(FORM_BF16X6, 2, 4, 2), KP_W(FORM_BF16X6, 4, 2, 2), KP_W(FORM_BF16X6, 4, 4, 1),
+};
+
+const Variant* find_wide(int form, const ModeTile& t) {
+  if (t.kind != 3) return nullptr;
+  for (const Variant& v : kWide)
+    if (v.form == form && v.nb == t.nb && v.fb == t.fb && v.bk == t.bk &&
+        (t.occ == 0 || v.occ == t.occ) && (t.pf == 0 || v.pf == t.pf))
+      return &v;
+  return nullptr;
+}
+
 const Variant* find_variant(int form, const ModeTile& t) {
   if (t.kind != 0) return nullptr;
   for (const Variant& v : kVariants)
@@ -114,7 +150,8 @@ const Variant* find_variant(int form, const ModeTile& t) {
 // blocks along n with 8-wide k chunks (small LDS and register footprint),
 // with two chunks of loads in flight once m >= 160; FP32 7 blocks (8 at
 // n <= 128, 4 at 128 < n <= 184) with two chunks of loads in flight; the
-// BF16 split forms 4 blocks (BF16x6 with two chunks in flight). Short
+// BF16 split forms 4 blocks (BF16x6 with two chunks in flight), or the wide
+// tile above n = 176 (see the end of pick_tile). Short
 // contractions (m <= 64; FP64: m <= 32, or m <= 64 on the lead layout)
 // take strip tiles.
 // 16-row blocks left empty in the last n tile when n is covered by tiles of
@@ -196,6 +233,15 @@ ModeTile pick_tile(int form, int64_t Il, int64_t m, int64_t n, int64_t Ir) {
       t.nb = 4; t.fb = 1; t.bk = 16; t.pf = 2;
     }
   }
+  // The split forms with n > 176 on the large-problem tile: the wide tile
+  // (factor rows split per wave in registers, 32 x 64 outputs per wave).
+  // Cube sweeps, us per mode, k-loop -> wide: BF16x6 n = 200 50 -> 35,
+  // 256 87 -> 61, 324 252 -> 179 (160: 22 -> 24, kept); BF16x3 n = 200
+  // 31 -> 29, 324 158 -> 129, but 256 52 -> 56, so BF16x3 keeps the k-loop
+  // tile when 64-row tiles cover n exactly (n = 192, 256).
+  if ((form == FORM_BF16X6 || form == FORM_BF16X3) && t.kind == 0 && t.nb == 4 && t.fb == 1 &&
+      n > 176 && !(form == FORM_BF16X3 && n % 64 == 0 && n <= 256))
+    t = ModeTile{2, 4, 32, 2, 2, 3};
   return t;
 }
 
@@ -213,9 +259,9 @@ ModeTile default_mode_tile(int form, const ModeArgs& a, bool alone) {
 
 bool resolve_mode_tile(int form, const ModeTile& t, ModeTile* out) {
   if (t.kind == 1) return strip_resolve(form, t, out);
-  const Variant* v = find_variant(form, t);
+  const Variant* v = t.kind == 3 ? find_wide(form, t) : find_variant(form, t);
   if (!v) return false;
-  *out = ModeTile{v->nb, v->fb, v->bk, v->occ, v->pf, 0};
+  *out = ModeTile{v->nb, v->fb, v->bk, v->occ, v->pf, t.kind};
   return true;
 }
 
@@ -240,6 +286,19 @@ int list_mode_variants(int form, int32_t* out, int cap) {
     }
     ++count;
   }
+  for (const Variant& v : kWide) {
+    if (v.form != form) continue;
+    if (count < cap) {
+      int32_t* o = out + 6 * count;
+      o[0] = v.nb;
+      o[1] = v.fb;
+      o[2] = v.bk;
+      o[3] = v.occ;
+      o[4] = v.pf;
+      o[5] = 3;
+    }
+    ++count;
+  }
   const int ns = list_strip_variants(form, count < cap ? out + 6 * count : nullptr,
                                      count < cap ? cap - count : 0);
   return count + ns;
@@ -249,7 +308,8 @@ hipError_t launch_mode(int form, const ModeArgs& a, const ModeTile* force,
                        hipStream_t stream) {
   const ModeTile t = force ? *force : default_mode_tile(form, a);
   const bool strip = t.kind == 1;
-  const Variant* v = strip ? nullptr : find_variant(form, t);
+  const bool wide = t.kind == 3;
+  const Variant* v = strip ? nullptr : (wide ? find_wide(form, t) : find_variant(form, t));
   ModeTile st{};
   if (strip && (!strip_resolve(form, t, &st) || a.m > st.bk)) return hipErrorInvalidValue;
   if (!strip && !v) return hipErrorInvalidValue;
@@ -265,8 +325,10 @@ hipError_t launch_mode(int form, const ModeArgs& a, const ModeTile* force,
   const int64_t lspan = ((a.n - 1) * a.rs + (a.m > 0 ? a.m - 1 : 0) * a.cs + 1) * es;
   if (lspan >= limit) return hipErrorInvalidValue;
   const int64_t per = (limit - 1) / (slab > 0 ? slab : 1);
-  const int64_t bf = 64 * t.fb;
-  const int64_t bn = 16 * t.nb;
+  // workgroup tile: k-loop tiles 16 nb rows x 64 fb fibers; wide tiles
+  // 64 nb rows x 16 fb fibers
+  const int64_t bf = strip ? 0 : (wide ? 16 * v->fb : 64 * v->fb);
+  const int64_t bn = strip ? 0 : (wide ? 64 * v->nb : 16 * v->nb);
   // 16-byte group loads: L k-contiguous with 16-byte aligned rows, m a
   // multiple of 16 bytes' worth of elements (so the k tail is whole 16-byte
   // pieces), and for the lead layout X rows (m elements) 16-byte aligned too

@@ -514,5 +514,7 @@ class BatchedTucker:
 
 def force_tile(nb=0, fb=0, bk=0, occ=0, pf=0, kind=0):
     """Force the mode-kernel tile for later launches (nb=0 resets); kind 1
-    selects a strip tile (bk = padded contraction length >= m)."""
+    selects a strip tile (bk = padded contraction length >= m), kind 3 a wide
+    tile of the BF16 split forms (nb 16-row blocks per wave, fb 16-fiber
+    blocks, bk 32)."""
     check(lib().kp_force_tile(nb, fb, bk, occ, pf, kind), "kp_force_tile")

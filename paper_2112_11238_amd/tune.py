@@ -63,7 +63,7 @@ def variants(form, batch=False, m=None):
     lib().kp_tile_variants(form, int(bool(batch)), buf, n)
     out = [tuple(buf[6 * i:6 * i + 6]) for i in range(n)]
     if m is not None:
-        out = [v for v in out if v[5] == 0 or m <= v[2]]
+        out = [v for v in out if v[5] != 1 or m <= v[2]]
     return out
 
 

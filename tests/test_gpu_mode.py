@@ -188,9 +188,11 @@ TILES = {
                  (8, 1, 16, 2), (7, 2, 16, 2), (13, 1, 16, 2), (4, 1, 16, 2, 2), (7, 1, 16, 2, 2),
                  (8, 1, 16, 2, 2)],
     "bf16x3": [(1, 4, 32, 2), (2, 4, 32, 2), (2, 2, 32, 2), (4, 2, 32, 2), (4, 1, 32, 2),
-               (8, 1, 32, 2), (7, 1, 32, 2), (1, 2, 32, 2), (2, 1, 32, 2), (4, 1, 32, 2, 2)],
+               (8, 1, 32, 2), (7, 1, 32, 2), (1, 2, 32, 2), (2, 1, 32, 2), (4, 1, 32, 2, 2),
+               (2, 4, 32, 2, 2, 3), (4, 2, 32, 2, 2, 3), (4, 4, 32, 1, 2, 3)],
     "bf16x6": [(1, 4, 32, 2), (2, 4, 32, 2), (2, 2, 32, 2), (4, 2, 32, 2), (4, 1, 32, 2),
-               (8, 1, 32, 2), (1, 2, 32, 2), (2, 1, 32, 2), (4, 1, 32, 2, 2)],
+               (8, 1, 32, 2), (1, 2, 32, 2), (2, 1, 32, 2), (4, 1, 32, 2, 2),
+               (2, 4, 32, 2, 2, 3), (4, 2, 32, 2, 2, 3), (4, 4, 32, 1, 2, 3)],
 }
 
 

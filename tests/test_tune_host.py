@@ -56,7 +56,10 @@ def test_variant_lists(lib, tune):
         strips = [v for v in mode if v[5] == 1]
         assert strips and all(v[3:5] == (0, 0) and v[2] in (16, 32, 48, 64) for v in strips)
         assert any(v[2] == 48 for v in strips) == (form == 0)      # FP64 only
-        assert all(v[5] == 0 or v[2] >= 40 for v in tune.variants(form, m=40))
+        assert all(v[5] != 1 or v[2] >= 40 for v in tune.variants(form, m=40))
+        # wide tiles (kind 3): the BF16 split forms only, 32-wide k steps
+        wide = [v for v in mode if v[5] == 3]
+        assert (len(wide) > 0) == (form in (3, 6)) and all(v[2] == 32 and v[4] == 2 for v in wide)
         assert len(tune.variants(form, m=200)) == len(mode) - len(strips)
     assert lib.kp_tile_variants(2, 0, None, 0) == -9
     assert lib.kp_tile_variants(0, 2, None, 0) == -9
