@@ -37,6 +37,21 @@ constexpr size_t wide_lds_bytes() {
   return 2 * FormT<FORM>::P * (16 * FBW * (4 / WN)) * (BK + 16 / sizeof(SE)) * sizeof(SE);
 }
 
+// Store of one value at per-lane byte offset off plus the wave-uniform
+// byte offset soff (the instruction's scalar offset).
+template <typename G>
+__device__ __forceinline__ void buffer_store_at(G v, __amdgpu_buffer_rsrc_t rs, uint32_t off,
+                                                uint32_t soff) {
+  if constexpr (sizeof(G) == 8) {
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), rs, static_cast<int>(off),
+                                          static_cast<int>(soff), 0);
+  } else {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), rs,
+                                          static_cast<int>(off), static_cast<int>(soff), 0);
+  }
+}
+
 template <int FORM, int NBW, int FBW, int WN, int BK, bool INNER, bool VEC>
 __device__ __forceinline__ void wide_tile(const ModeArgs& a, int64_t bx, int64_t by,
                                           char* __restrict__ lds) {
@@ -328,10 +343,16 @@ __device__ __forceinline__ void wide_tile(const ModeArgs& a, int64_t bx, int64_t
 
   // Store (as mode_tile): the MFMA column lane & 15 is the memory-contiguous
   // output index; rows past n and fibers past F get an offset past the
-  // resource and the hardware drops the store.
+  // resource and the hardware drops the store. A plain store (no
+  // accumulation) of a block that lies wholly inside the output takes one
+  // per-lane offset per block: accumulator items v step the row (inner) or
+  // the fiber (lead) by RV*v, a uniform byte step passed as the scalar
+  // offset, so the stores need no per-item address arithmetic.
   constexpr uint32_t kDrop = 0x80000000u;
+  constexpr uint32_t RV = FORM == FORM_F64 ? 4 : 1;  // row(lane, v) - row(lane, 0) = RV v
   const auto yrs = __builtin_amdgcn_make_buffer_rsrc(
       Y, 0, static_cast<int>(a.Il * n * a.Ir * ES), kBufferFlags);
+  const bool plain = a.accumulate == kAccNone;
 #pragma unroll
   for (int q = 0; q < (INNER ? NBW : FBW); ++q)
 #pragma unroll
@@ -342,6 +363,13 @@ __device__ __forceinline__ void wide_tile(const ModeArgs& a, int64_t bx, int64_t
       if constexpr (INNER) {
         const uint32_t r = f032 + wf * 16 * FBW + p * 16 + c;
         const uint32_t yb = fiber_offset(r < F32 ? r : 0, Il32, n32);
+        const uint32_t rowb = i032 + (wn * NBW + q) * 16;  // the block's first row
+        if (plain && rowb + 16 <= n32 && f032 + BF <= F32) {
+          const uint32_t vb = (yb + Il32 * (rowb + FT::row(lane, 0))) * ES;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) buffer_store_at<G>(val[v], yrs, vb, Il32 * ES * RV * v);
+          continue;
+        }
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const uint32_t i = i032 + (wn * NBW + q) * 16 + FT::row(lane, v);
@@ -349,6 +377,13 @@ __device__ __forceinline__ void wide_tile(const ModeArgs& a, int64_t bx, int64_t
         }
       } else {
         const uint32_t i = i032 + (wn * NBW + p) * 16 + c;
+        const uint32_t fb0 = f032 + wf * 16 * FBW + q * 16;  // the block's first fiber
+        if (plain && i032 + (wn * NBW + p) * 16 + 16 <= n32 && fb0 + 16 <= F32) {
+          const uint32_t vb = (i + n32 * (fb0 + FT::row(lane, 0))) * ES;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) buffer_store_at<G>(val[v], yrs, vb, n32 * ES * RV * v);
+          continue;
+        }
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const uint32_t f = f032 + wf * 16 * FBW + q * 16 + FT::row(lane, v);
