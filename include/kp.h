@@ -142,6 +142,11 @@ int kp_kronsum(const kp_tensor* T, const kp_matrix* const A[], kp_tensor* S, int
  * operator does not depend on the order, Sec. 2); ties keep 1..d.
  * Intermediates live in the workspace `ws` (ws_bytes >= kp_tucker_workspace);
  * with a cache they are written into the cache instead and ws may be NULL.
+ * For the BF16 split forms kp_tucker_workspace also counts the factors'
+ * bf16 planes, split once per call for the products that run on wide tiles;
+ * a workspace that holds only the intermediates is accepted (those products
+ * then split their factor rows themselves; the result is the same bit for
+ * bit).
  * If `cache` is non-NULL it receives the forward partial products
  * P_k = T x_1 L_1 ... x_k L_k for k = 1..d-1 in definition order, packed one
  * after another as column-major tensors (cache_bytes >= kp_tucker_cache_size);

@@ -209,6 +209,19 @@ void chain_ws(const ChainPlan& p, size_t esize, size_t* off1, size_t* total) {
   *total = (p.count > 2 ? 2 : (p.count > 1 ? 1 : 0)) * align_up(big);
 }
 
+// Bytes of the pre-split factor planes a chain may use (the BF16 split
+// forms: one plane set per non-identity factor, whichever tile its product
+// runs on), placed after the chain's intermediates.
+size_t chain_planes_bytes(const ChainPlan& p, const kp_matrix* const* L, int form) {
+  if (form != FORM_BF16X3 && form != FORM_BF16X6) return 0;
+  size_t total = 0;
+  for (int s = 0; s < p.count; ++s) {
+    const kp_matrix& f = *L[p.order[s]];
+    total += align_up(split_planes_bytes(form, f.rows, f.cols));
+  }
+  return total;
+}
+
 // Whether steps s and s + 1 of a chain without a cache run as one fused pass
 // (modes k and k + 1 in that order, both short; the strided pair for
 // I_l > 1, the lead-layout pair for I_l = 1); fills the pass's arguments
@@ -429,12 +442,14 @@ int kp_kronsum(const kp_tensor* T, const kp_matrix* const* A, kp_tensor* S, int 
 
 size_t kp_tucker_workspace(const kp_tensor* T, const kp_matrix* const* L, int prec) {
   if (validate_tucker_args(T, L, prec)) return 0;
-  // exactly what kp_tucker checks on its workspace path (no cache)
+  // the intermediates (what kp_tucker requires on its workspace path, no
+  // cache) and, for the BF16 split forms, the factors' pre-split planes
+  // (used when the workspace has room for them)
   ChainPlan p;
   make_chain(*T, L, false, &p);
   size_t off1, total;
   chain_ws(p, elem_size(T->dtype), &off1, &total);
-  return total;
+  return total + chain_planes_bytes(p, L, form_of(prec, T->dtype));
 }
 
 int kp_tucker_order(const kp_tensor* T, const kp_matrix* const* L, int* order, int* count) {
@@ -475,9 +490,20 @@ int kp_tucker(const kp_tensor* T, const kp_matrix* const* L, kp_tensor* S, int p
   const size_t need_cache = cache ? cache_bytes_for(*T, L) : 0;
   if (cache && cache_bytes < need_cache) return KP_ERR_WORKSPACE;
   size_t off1 = 0, need = 0;
+  const int form = form_of(prec, T->dtype);
+  // pre-split factor planes after the intermediates, when the workspace has
+  // room for them (kp_tucker_workspace counts them; a smaller workspace that
+  // holds the intermediates runs the products with in-register splits)
+  size_t planes_at = 0, planes_need = 0;
   if (!cache) {
     chain_ws(p, es, &off1, &need);
     if (need > 0 && (!ws || ws_bytes < need)) return KP_ERR_WORKSPACE;
+    const size_t pb = chain_planes_bytes(p, L, form);
+    if (pb > 0 && ws && ws_bytes >= align_up(need) + pb) {
+      planes_at = align_up(need);
+      planes_need = pb;
+      need = planes_at + pb;
+    }
   }
   // Buffers the chain writes (the used part of ws, the cache) must not
   // overlap anything it reads or writes elsewhere.
@@ -492,7 +518,6 @@ int kp_tucker(const kp_tensor* T, const kp_matrix* const* L, kp_tensor* S, int p
   if (need_cache > 0 &&
       (hits_inputs(cache, need_cache) || overlaps(cache, need_cache, ws, ws ? ws_bytes : 0)))
     return KP_ERR_ALIAS;
-  const int form = form_of(prec, T->dtype);
   if (numel(*S) == 0) return KP_OK;
   if (p.count == 0) {
     // every factor is the identity: S = T
@@ -513,6 +538,43 @@ int kp_tucker(const kp_tensor* T, const kp_matrix* const* L, kp_tensor* S, int p
   // fusion plan says so (never with a cache, which must hold every partial)
   bool fused[KP_MAX_ORDER] = {};
   if (!cache) plan_fusion(p, T->d, L, form, fused);
+  // products on wide tiles read their factor's planes, split by one launch
+  // before the chain
+  const void* planes[KP_MAX_ORDER] = {};
+  if (planes_need > 0) {
+    // the steps that run as single products (as the loop below pairs them)
+    bool single[KP_MAX_ORDER] = {};
+    for (int s = 0; s < p.count; ++s) {
+      tile::PairArgs probe;
+      if (fused[s] && fuse_step(p, s, T->d, L, form, &probe)) {
+        ++s;
+        continue;
+      }
+      single[s] = true;
+    }
+    SplitJobs jobs{};
+    size_t at = planes_at;
+    for (int s = 0; s < p.count; ++s) {
+      const int k = p.order[s];
+      void* dst = static_cast<char*>(ws) + at;
+      at += align_up(split_planes_bytes(form, L[k]->rows, L[k]->cols));
+      if (!single[s]) continue;
+      const ModeArgs a = mode_args(nullptr, nullptr, p.dims[s], T->d, k, *L[k], 0);
+      if (!mode_uses_wide(form, a, tile_override())) continue;
+      SplitJob& J = jobs.job[jobs.count++];
+      J.L = L[k]->data;
+      J.n = L[k]->rows;
+      J.m = L[k]->cols;
+      J.rs = L[k]->rs;
+      J.cs = L[k]->cs;
+      J.planes = dst;
+      J.begin = jobs.total;
+      jobs.total += split_planes_tasks(J.n, J.m);
+      planes[s] = dst;
+    }
+    st = hip_status(launch_split_planes(form, jobs, stream));
+    if (st) return st;
+  }
   for (int s = 0; s < p.count; ++s) {
     const int k = p.order[s];
     tile::PairArgs pa;
@@ -528,7 +590,7 @@ int kp_tucker(const kp_tensor* T, const kp_matrix* const* L, kp_tensor* S, int p
     void* dst = dst_of(s);
     if (cache && s < p.count - 1) cache_off += align_up(static_cast<size_t>(p.size[s + 1]) * es);
     const ModeArgs a = mode_args(src, dst, p.dims[s], T->d, k, *L[k], 0);
-    st = hip_status(launch_mode(form, a, tile_override(), stream));
+    st = hip_status(launch_mode_planes(form, a, tile_override(), planes[s], stream));
     if (st) return st;
     src = dst;
   }

@@ -45,4 +45,28 @@ hipError_t launch_gram_product(int form, const void* Q, const void* P, int64_t I
                                int64_t m, int64_t Ir, void* part, void* dL, int64_t rs, int64_t cs,
                                const kp_matrix& L, void* Y, hipStream_t stream);
 
+// Pre-split factor planes of the BF16 split forms' wide tiles (wide_tile.h):
+// bytes for an n x m factor, whether a product runs on a wide tile (and so
+// can read planes), one launch splitting up to KP_MAX_ORDER FP32 factors,
+// and a product launch reading a factor's planes (nullptr: the tile splits
+// the factor itself).
+struct SplitJob {
+  const void* L;
+  int64_t n, m, rs, cs;
+  void* planes;
+  int64_t begin;  // first task (one lane of one block and step) of this job
+};
+struct SplitJobs {
+  SplitJob job[KP_MAX_ORDER];
+  int count;
+  int64_t total;
+};
+size_t split_planes_bytes(int form, int64_t n, int64_t m);
+// Tasks (one lane of one 16-row block and 32-wide k step) of one factor.
+int64_t split_planes_tasks(int64_t n, int64_t m);
+bool mode_uses_wide(int form, const ModeArgs& a, const ModeTile* force);
+hipError_t launch_split_planes(int form, const SplitJobs& jobs, hipStream_t stream);
+hipError_t launch_mode_planes(int form, const ModeArgs& a, const ModeTile* force,
+                              const void* planes, hipStream_t stream);
+
 }  // namespace kp

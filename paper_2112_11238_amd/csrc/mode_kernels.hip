@@ -22,6 +22,7 @@
 // and the partial products are accumulated in FP32, the leading product in
 // its own accumulator and all correction products in a second one.
 #include "kp_common.h"
+#include "kp_internal.h"
 #include "mode_tile.h"
 #include "wide_tile.h"
 
@@ -59,13 +60,34 @@ __global__ __launch_bounds__(kThreads, OCC) void mode_kernel(ModeArgs a, int64_t
 // Wide tiles of the BF16 split forms (wide_tile.h): the four waves split the
 // n rows (NBW 16-row blocks each) and share FBW 16-fiber blocks; 32-wide k
 // steps.
-template <int FORM, int NBW, int FBW, int OCC, bool INNER, bool VEC>
+// PRE: a.L points at the factor's pre-split planes (split_planes_kernel).
+template <int FORM, int NBW, int FBW, int OCC, bool INNER, bool VEC, bool PRE = false>
 __global__ __launch_bounds__(kThreads, OCC) void wide_kernel(ModeArgs a, int64_t gx,
                                                              int64_t gy) {
   __shared__ __attribute__((aligned(16))) char lds[wide_lds_bytes<FORM, FBW, 4, 32>()];
   int64_t bx, by;
   xcd_tile(gx, gy, &bx, &by);
-  wide_tile<FORM, NBW, FBW, 4, 32, INNER, VEC>(a, bx, by, lds);
+  wide_tile<FORM, NBW, FBW, 4, 32, INNER, VEC, PRE>(a, bx, by, lds);
+}
+
+// The bf16 planes of up to KP_MAX_ORDER factors in one launch; thread t
+// (grid-stride) writes one lane's fragments of one (block, step) of the
+// factor whose task range holds it.
+template <int FORM>
+__global__ __launch_bounds__(kThreads) void split_planes_kernel(SplitJobs jobs) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * kThreads;
+  for (int64_t t = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; t < jobs.total;
+       t += stride) {
+    int j = 0;
+    while (j + 1 < jobs.count && t >= jobs.job[j + 1].begin) ++j;
+    const SplitJob& J = jobs.job[j];
+    const int64_t r = t - J.begin;
+    const int lane = static_cast<int>(r & 63);
+    const int64_t steps = (J.m + 31) / 32;
+    const int64_t s = (r >> 6) % steps, b = (r >> 6) / steps;
+    split_planes_lane<FORM>(static_cast<const float*>(J.L), J.n, J.m, J.rs, J.cs, b, s, lane,
+                            static_cast<bf16x8_t*>(J.planes));
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -126,6 +148,18 @@ const Variant kWide[] = {
     KP_W(FORM_BF16X3, 2, 4, 2), KP_W(FORM_BF16X3, 4, 2, 2), KP_W(FORM_BF16X3, 4, 4, 1),
     KP_W(FORM_BF16X6, 2, 4, 2), KP_W(FORM_BF16X6, 4, 2, 2), KP_W(FORM_BF16X6, 4, 4, 1),
 };
+// The same tiles reading pre-split planes, in the same order: kernel[inner][vec].
+#define KP_WP(FORM, NBW, FBW, OCC)                                                  \
+  {FORM, NBW, FBW, 32, OCC, 2,                                                      \
+   {{wide_kernel<FORM, NBW, FBW, OCC, false, false, true>,                          \
+     wide_kernel<FORM, NBW, FBW, OCC, false, true, true>},                          \
+    {wide_kernel<FORM, NBW, FBW, OCC, true, false, true>,                           \
+     wide_kernel<FORM, NBW, FBW, OCC, true, true, true>}}}
+const Variant kWidePre[] = {
+    KP_WP(FORM_BF16X3, 2, 4, 2), KP_WP(FORM_BF16X3, 4, 2, 2), KP_WP(FORM_BF16X3, 4, 4, 1),
+    KP_WP(FORM_BF16X6, 2, 4, 2), KP_WP(FORM_BF16X6, 4, 2, 2), KP_WP(FORM_BF16X6, 4, 4, 1),
+};
+static_assert(sizeof(kWide) == sizeof(kWidePre), "one planes kernel per wide tile");
 
 const Variant* find_wide(int form, const ModeTile& t) {
   if (t.kind != 3) return nullptr;
@@ -304,12 +338,47 @@ int list_mode_variants(int form, int32_t* out, int cap) {
   return count + ns;
 }
 
+size_t split_planes_bytes(int form, int64_t n, int64_t m) {
+  if (n <= 0 || m <= 0) return 0;
+  const int64_t frags = form == FORM_BF16X6 ? split_plane_frags<FORM_BF16X6>(n, m)
+                                            : split_plane_frags<FORM_BF16X3>(n, m);
+  return static_cast<size_t>(frags) * sizeof(bf16x8_t);
+}
+
+int64_t split_planes_tasks(int64_t n, int64_t m) {
+  return n > 0 && m > 0 ? ((n + 15) / 16) * ((m + 31) / 32) * 64 : 0;
+}
+
+bool mode_uses_wide(int form, const ModeArgs& a, const ModeTile* force) {
+  if (form != FORM_BF16X3 && form != FORM_BF16X6) return false;
+  const ModeTile t = force ? *force : default_mode_tile(form, a);
+  return t.kind == 3 && find_wide(form, t) != nullptr;
+}
+
+hipError_t launch_split_planes(int form, const SplitJobs& jobs, hipStream_t stream) {
+  if (jobs.count <= 0 || jobs.total <= 0) return hipSuccess;
+  if (form != FORM_BF16X3 && form != FORM_BF16X6) return hipErrorInvalidValue;
+  int64_t blocks = (jobs.total + kThreads - 1) / kThreads;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(form == FORM_BF16X6 ? split_planes_kernel<FORM_BF16X6>
+                                         : split_planes_kernel<FORM_BF16X3>,
+                     dim3(static_cast<unsigned>(blocks)), dim3(kThreads), 0, stream, jobs);
+  return hipGetLastError();
+}
+
 hipError_t launch_mode(int form, const ModeArgs& a, const ModeTile* force,
                        hipStream_t stream) {
+  return launch_mode_planes(form, a, force, nullptr, stream);
+}
+
+hipError_t launch_mode_planes(int form, const ModeArgs& a, const ModeTile* force,
+                              const void* planes, hipStream_t stream) {
   const ModeTile t = force ? *force : default_mode_tile(form, a);
   const bool strip = t.kind == 1;
   const bool wide = t.kind == 3;
   const Variant* v = strip ? nullptr : (wide ? find_wide(form, t) : find_variant(form, t));
+  // a wide tile with the factor's pre-split planes runs their kernel
+  if (wide && v && planes) v = &kWidePre[v - kWide];
   ModeTile st{};
   if (strip && (!strip_resolve(form, t, &st) || a.m > st.bk)) return hipErrorInvalidValue;
   if (!strip && !v) return hipErrorInvalidValue;
@@ -351,6 +420,7 @@ hipError_t launch_mode(int form, const ModeArgs& a, const ModeTile* force,
     // one-dimensional grid: its size in work-items must fit 32 bits
     if (gx * gy > 0xffffffffLL / kThreads) return hipErrorInvalidConfiguration;
     const bool vec = vec_l && (inner || (xrow16 && reinterpret_cast<uintptr_t>(p.X) % 16 == 0));
+    if (wide && planes) p.L = planes;
     hipLaunchKernelGGL(v->kernel[inner ? 1 : 0][vec ? 1 : 0],
                        dim3(static_cast<unsigned>(gx * gy)), dim3(kThreads), 0, stream, p, gx,
                        gy);

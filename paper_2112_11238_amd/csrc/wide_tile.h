@@ -11,6 +11,9 @@
 //   * the input fibers are shared by the four waves, so they are staged once
 //     per workgroup through LDS (as bf16 planes for the split forms), double
 //     buffered, with two chunks of global loads in flight.
+// A Tucker call may split every factor once instead (split_planes below):
+// the wave then loads its rows' fragments as bf16 planes (PRE), the same
+// values the in-register split gives.
 // No factor chunk is written to or read from LDS, and each wave issues more
 // products per barrier. This pays for the split forms, whose products are
 // short next to their operand fetches; the FP64 and FP32 forms, compiled
@@ -52,7 +55,39 @@ __device__ __forceinline__ void buffer_store_at(G v, __amdgpu_buffer_rsrc_t rs, 
   }
 }
 
-template <int FORM, int NBW, int FBW, int WN, int BK, bool INNER, bool VEC>
+// Pre-split factor planes (split forms): for every 16-row block of L
+// (ceil(n/16) blocks), every 32-wide k step (ceil(m/32)) and every plane,
+// the 64 lanes' MFMA fragments, lane l holding rows 16 b + l % 16 and k
+// values 32 s + 8 (l / 16) .. + 7 (zero past k = m): 1 KB per (block,
+// step, plane), stored in that order.
+template <int FORM>
+__host__ __device__ constexpr int64_t split_plane_frags(int64_t n, int64_t m) {
+  return ((n + 15) / 16) * ((m + 31) / 32) * FormT<FORM>::P * 64;
+}
+
+// One lane's fragments (all planes) of block b, step s of L (FP32, element
+// (i, k) at L[i rs + k cs], n x m), written to planes.
+template <int FORM>
+__device__ __forceinline__ void split_planes_lane(const float* __restrict__ L, int64_t n, int64_t m,
+                                                  int64_t rs, int64_t cs, int64_t b, int64_t s,
+                                                  int lane, bf16x8_t* __restrict__ planes) {
+  constexpr int P = FormT<FORM>::P;
+  int64_t i = 16 * b + (lane & 15);
+  i = i < n ? i : n - 1;
+  float v[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int64_t k = 32 * s + 8 * (lane >> 4) + e;
+    v[e] = k < m ? L[i * rs + k * cs] : 0.0f;
+  }
+  bf16x8_t pl[P];
+  split_bf16_group<P, 8>(v, pl);
+  const int64_t steps = (m + 31) / 32;
+#pragma unroll
+  for (int p = 0; p < P; ++p) planes[((b * steps + s) * P + p) * 64 + lane] = pl[p];
+}
+
+template <int FORM, int NBW, int FBW, int WN, int BK, bool INNER, bool VEC, bool PRE = false>
 __device__ __forceinline__ void wide_tile(const ModeArgs& a, int64_t bx, int64_t by,
                                           char* __restrict__ lds) {
   using FT = FormT<FORM>;
@@ -72,6 +107,7 @@ __device__ __forceinline__ void wide_tile(const ModeArgs& a, int64_t bx, int64_t
   constexpr int LDK = BK + 16 / static_cast<int>(sizeof(SE));  // row stride: +16 bytes
   constexpr int XT = (BF * KG + kThreads - 1) / kThreads;
   static_assert(WN * WF == 4 && BK % MK == 0, "tile shape");
+  static_assert(!PRE || SPLIT, "pre-split planes are for the split forms");
   static_assert(!INNER || kThreads % BF == 0, "BF must divide the block size");
 
   typedef SE XTile[P][BF][LDK];
@@ -142,7 +178,9 @@ __device__ __forceinline__ void wide_tile(const ModeArgs& a, int64_t bx, int64_t
   constexpr int NQ = KV / PER;       // 16-byte pieces per group of KV values
 
   G xr[2][XT][KV];
-  G lv[NBW][KV];
+  G lv[NBW][KV];       // the next step's factor values (in-register split)
+  FragT lnext[NBW][P];  // the next step's factor fragments (PRE: a.L holds the planes)
+  const int64_t lblocks = (n + 15) / 16;
 
   // Chunk ch of X (k0 = ch*BK) into register set SET; CHECK: the chunk
   // reaches past k = m (those k read as zero through the resource bound).
@@ -206,6 +244,20 @@ __device__ __forceinline__ void wide_tile(const ModeArgs& a, int64_t bx, int64_t
   // Macro step s (k0 = MK s) of this wave's factor rows into lv.
   auto load_l = [&](int64_t s, auto check) {
     constexpr bool CHECK = decltype(check)::value;
+    if constexpr (PRE) {
+      // the planes hold zeros past k = m: no check; blocks past the last one
+      // (rows past n, never stored) read the last block
+      const FragT* __restrict__ Lp = static_cast<const FragT*>(a.L);
+      const int64_t steps = (m + MK - 1) / MK;
+#pragma unroll
+      for (int nb = 0; nb < NBW; ++nb) {
+        int64_t b = i032 / 16 + wn * NBW + nb;
+        b = b < lblocks ? b : lblocks - 1;
+#pragma unroll
+        for (int p = 0; p < P; ++p) lnext[nb][p] = Lp[((b * steps + s) * P + p) * 64 + lane];
+      }
+      return;
+    }
     const int64_t k0 = s * MK;
     const uint32_t lk = static_cast<uint32_t>(k0 * a.cs * ES);
     const auto rs = __builtin_amdgcn_make_buffer_rsrc(
@@ -260,8 +312,15 @@ __device__ __forceinline__ void wide_tile(const ModeArgs& a, int64_t bx, int64_t
   auto step = [&](int buf, int kk, int64_t s, auto steady) {
     constexpr bool STEADY = decltype(steady)::value;
     FragT la[NBW][P];
+    if constexpr (PRE) {
 #pragma unroll
-    for (int nb = 0; nb < NBW; ++nb) to_frag(lv[nb], la[nb]);
+      for (int nb = 0; nb < NBW; ++nb)
+#pragma unroll
+        for (int p = 0; p < P; ++p) la[nb][p] = lnext[nb][p];
+    } else {
+#pragma unroll
+      for (int nb = 0; nb < NBW; ++nb) to_frag(lv[nb], la[nb]);
+    }
     if constexpr (STEADY) {
       load_l(s + 1, Unchecked{});
     } else if (s + 1 < nsteps) {

@@ -147,3 +147,63 @@ def test_cube200_graph_replay(kp, dt, prec):
         torch.cuda.synchronize()
         assert torch.equal(Sg, want), r
         assert torch.isfinite(other).all()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("prec", ["bf16x3", "bf16x6"])
+def test_presplit_planes_bitwise(kp, prec):
+    """BF16 products on wide tiles (n > 176) read factor planes split once
+    per kp_tucker call. The same call with a workspace that holds only the
+    intermediates (each tile then splits its rows itself) and the chain of
+    kp_mump calls in kp_tucker's order must agree with it bit for bit, and
+    all of them with the FP64 oracle within the split form's bound.
+    Ragged sizes: rows past n in the last tile and a k tail in the last step."""
+    import ctypes
+    from paper_2112_11238_amd import ops
+    rng = np.random.default_rng(29)
+    tshape = (181, 200, 197)                 # torch order (mode d first)
+    nrows = (204, 185, 200)                  # factor rows, torch order
+    T = rng.standard_normal(tshape)
+    Ls = [rng.standard_normal((nrows[j], tshape[j])) / np.sqrt(tshape[j]) for j in range(3)]
+    Td = to_dev(T, torch.float32)
+    Ld = [to_dev(L, torch.float32) for L in Ls]
+    say("presplit planes", prec)
+    S_full = kp.tucker(Td, Ld, prec=prec)
+
+    # kp_tucker with a workspace that holds only the intermediates
+    lb = ops.lib()
+    td = ops._tdesc(ops._canon(Td), True)
+    arr = ops._mlist([ops._mdesc(L) for L in Ld][::-1])
+    p = ops._prec(prec)
+    full = lb.kp_tucker_workspace(ctypes.byref(td), arr, p)
+    S_inreg = torch.empty_like(S_full)
+    sd = ops._tdesc(S_inreg, True)
+    order = (ctypes.c_int * 8)()
+    cnt = ctypes.c_int()
+    assert lb.kp_tucker_order(ctypes.byref(td), arr, order, ctypes.byref(cnt)) == 0
+    # intermediates only: the largest intermediate, twice (column-major dims)
+    dims = list(tshape[::-1])
+    nrev = list(nrows[::-1])
+    big = 0
+    for s in range(cnt.value - 1):
+        k = order[s] - 1
+        dims[k] = nrev[k]
+        big = max(big, int(np.prod(dims)) * 4)
+    inter = 2 * ((big + 255) // 256 * 256)
+    assert inter < full                       # the planes take room of their own
+    ws = torch.empty(inter, dtype=torch.uint8, device=Td.device)
+    st = lb.kp_tucker(ctypes.byref(td), arr, ctypes.byref(sd), p, ws.data_ptr(), inter,
+                      None, 0, ops._stream())
+    assert st == 0
+    # the same products one by one (torch mode index = d - column-major mode)
+    X = Td
+    for s in range(cnt.value):
+        mu_cm = order[s]
+        X = kp.mump(X, Ld[3 - mu_cm], 4 - mu_cm, prec=prec)
+    torch.cuda.synchronize()
+    assert torch.equal(S_full, S_inreg)
+    assert torch.equal(S_full, X)
+    T64, L64 = cast64(T, torch.float32), [cast64(L, torch.float32) for L in Ls]
+    ref = oracle.tucker(T64, L64)
+    assert np.all(np.abs(S_full.double().cpu().numpy() - ref)
+                  <= chain_bound(T64, L64, prec, torch.float32))
