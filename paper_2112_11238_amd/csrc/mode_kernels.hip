@@ -268,13 +268,15 @@ ModeTile pick_tile(int form, int64_t Il, int64_t m, int64_t n, int64_t Ir) {
     }
   }
   // The split forms with n > 176 on the large-problem tile: the wide tile
-  // (factor rows split per wave in registers, 32 x 64 outputs per wave).
-  // Cube sweeps, us per mode, k-loop -> wide: BF16x6 n = 200 50 -> 35,
-  // 256 87 -> 61, 324 252 -> 179 (160: 22 -> 24, kept); BF16x3 n = 200
-  // 31 -> 29, 324 158 -> 129, but 256 52 -> 56, so BF16x3 keeps the k-loop
-  // tile when 64-row tiles cover n exactly (n = 192, 256).
+  // (32 x 64 outputs per wave, each wave with its own factor rows). Cube
+  // sweeps, us per mode, k-loop -> wide with the rows split in registers
+  // (kp_mump): BF16x6 n = 200 50 -> 35, 256 87 -> 61, 324 252 -> 179;
+  // BF16x3 n = 200 31 -> 29, 324 158 -> 129, 256 52 -> 56. us per Tucker
+  // step with the factor planes split once (kp_tucker): BF16x3 n = 256
+  // 159 -> 138, 324 504 -> 387; BF16x6 256 271 -> 176. At n = 160 the
+  // k-loop tile stays ahead (BF16x3 43 against 54 us per step).
   if ((form == FORM_BF16X6 || form == FORM_BF16X3) && t.kind == 0 && t.nb == 4 && t.fb == 1 &&
-      n > 176 && !(form == FORM_BF16X3 && n % 64 == 0 && n <= 256))
+      n > 176)
     t = ModeTile{2, 4, 32, 2, 2, 3};
   return t;
 }
