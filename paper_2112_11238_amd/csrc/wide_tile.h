@@ -309,6 +309,11 @@ __device__ __forceinline__ void wide_tile(const ModeArgs& a, int64_t bx, int64_t
   // factor rows into fragments, start loading the next step's, read the
   // fibers' planes and issue the products. STEADY: the next step is full
   // (no check, no branch).
+  // A wave whose n blocks all lie past n (the same in every lane) reads no
+  // fragments and issues no products; it still stages fibers and meets
+  // every barrier, and leaves its SIMD's matrix core to the other waves.
+  const bool idle = __builtin_amdgcn_readfirstlane(
+      static_cast<int>(static_cast<int64_t>(i032) + wn * NBW * 16 >= n));
   auto step = [&](int buf, int kk, int64_t s, auto steady) {
     constexpr bool STEADY = decltype(steady)::value;
     FragT la[NBW][P];
@@ -329,6 +334,7 @@ __device__ __forceinline__ void wide_tile(const ModeArgs& a, int64_t bx, int64_t
       else
         load_l(s + 1, Checked{});
     }
+    if (idle) return;
     FragT xa[FBW][P];
 #pragma unroll
     for (int fb = 0; fb < FBW; ++fb)
@@ -423,6 +429,7 @@ __device__ __forceinline__ void wide_tile(const ModeArgs& a, int64_t bx, int64_t
         const uint32_t r = f032 + wf * 16 * FBW + p * 16 + c;
         const uint32_t yb = fiber_offset(r < F32 ? r : 0, Il32, n32);
         const uint32_t rowb = i032 + (wn * NBW + q) * 16;  // the block's first row
+        if (rowb >= n32) continue;                          // wholly past n
         if (plain && rowb + 16 <= n32 && f032 + BF <= F32) {
           const uint32_t vb = (yb + Il32 * (rowb + FT::row(lane, 0))) * ES;
 #pragma unroll
@@ -435,6 +442,7 @@ __device__ __forceinline__ void wide_tile(const ModeArgs& a, int64_t bx, int64_t
           off[v] = (r < F32 && i < n32) ? (yb + Il32 * i) * ES : kDrop;
         }
       } else {
+        if (i032 + (wn * NBW + p) * 16 >= n32) continue;  // wholly past n
         const uint32_t i = i032 + (wn * NBW + p) * 16 + c;
         const uint32_t fb0 = f032 + wf * 16 * FBW + q * 16;  // the block's first fiber
         if (plain && i032 + (wn * NBW + p) * 16 + 16 <= n32 && fb0 + 16 <= F32) {
