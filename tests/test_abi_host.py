@@ -415,6 +415,26 @@ def test_workspace_sizes(lib, L):
     assert lib.kp_tucker_cache_size(ctypes.byref(T6), arr6) == want
 
 
+def test_workspace_counts_split_planes(lib, L):
+    # BF16 split forms: after the intermediates, one plane set per factor:
+    # ceil(n/16) row blocks x ceil(m/32) k steps x P planes x 1 KB (64 lanes
+    # x 8 bf16), each set rounded to 256 bytes; FP32 native counts none
+    dims, rows = [181, 200, 197], [204, 185, 200]
+    T = tensor(L, dims, dtype=1)
+    arr = mlist(L, [matrix(L, rows[k], dims[k], 1) for k in range(3)])
+    base = lib.kp_tucker_workspace(ctypes.byref(T), arr, 0)
+    assert base > 0
+    for prec, planes in ((3, 2), (6, 3)):
+        want = sum((((n + 15) // 16) * ((m + 31) // 32) * planes * 1024 + 255) // 256 * 256
+                   for n, m in zip(rows, dims))
+        assert lib.kp_tucker_workspace(ctypes.byref(T), arr, prec) == base + want
+    # a single product still gets its planes (no intermediates)
+    T1 = tensor(L, [200, 64], dtype=1)
+    arr1 = mlist(L, [matrix(L, 200, 200, 1), None])
+    assert lib.kp_tucker_workspace(ctypes.byref(T1), arr1, 0) == 0
+    assert lib.kp_tucker_workspace(ctypes.byref(T1), arr1, 6) == 13 * 7 * 3 * 1024
+
+
 @pytest.mark.parametrize("seed", range(8))
 def test_planned_order_minimises_flops(lib, L, seed):
     rng = np.random.default_rng(900 + seed)
