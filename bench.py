@@ -391,12 +391,24 @@ def main():
 # The other configurations (not the headline line): --workload NAME
 # ---------------------------------------------------------------------------
 
+# Seconds of back-to-back untimed calls before every timed run of the other
+# configurations: the GPU's clock ramps up under a sustained load, and a few
+# warm-up calls of a short kernel end before it has.
+WARM_S = 0.3
+
+
 def _events_ms(fn, steps, warmup):
     """Average ms per call of fn() over `steps` calls, events on the current
-    stream around the whole run (inputs resident, warm)."""
+    stream around the whole run (inputs resident, warm: at least `warmup`
+    untimed calls and WARM_S seconds of them)."""
     import torch
-    for _ in range(warmup):
+    t0 = time.perf_counter()
+    i = 0
+    while i < warmup or time.perf_counter() - t0 < WARM_S:
         fn()
+        i += 1
+        if i % 32 == 0:
+            torch.cuda.synchronize()  # wall time then tracks the GPU's
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -432,8 +444,7 @@ def _launch_ms(kp, dtype, prec, view, steps):
     X = torch.randn((Ir, m, Il), dtype=dtype, device="cuda")
     L = torch.randn((n, m), dtype=dtype, device="cuda")
     Y = torch.empty((Ir, n, Il), dtype=dtype, device="cuda")
-    for _ in range(2):
-        kp.mump(X, L, 2, prec=prec, out=Y)
+    _events_ms(lambda: kp.mump(X, L, 2, prec=prec, out=Y), 1, 2)  # warm-up, as every timed run
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * steps)]
     for k in range(steps):
         ev[2 * k].record()
@@ -449,7 +460,8 @@ def _views(kp, Td, Lds, prec, which="forward"):
 
 def _line(args, metric, value, unit, ms, dtype, workload, extra, higher=True):
     line = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
-            "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": higher,
+            "warmup": args.warmup, "warm_s": WARM_S, "ms_per_step": ms,
+            "higher_is_better": higher,
             "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic",
             "config": workload}
     line.update(extra)
