@@ -203,8 +203,12 @@ int kp_tucker_noalloc(const kp_tensor* T, const kp_matrix* const* L, kp_tensor* 
  * and then the imaginary part of the factor, the second adding i (or -i for
  * the conjugate transpose) times its result in its epilogue. prec as for
  * kp_mump (the split forms need F32).
- * The factor parts are first packed, as applied, into the workspace.
- * ws_bytes >= kp_tucker_complex_workspace(...). Errors: as kp_tucker, and
+ * The factor parts are first packed, as applied, into the workspace; for the
+ * BF16 split forms the workspace also holds each part's pre-split bf16
+ * planes (as for kp_tucker), read by the products that run on wide tiles.
+ * ws_bytes >= kp_tucker_complex_workspace(...); a workspace without room
+ * for the planes (the intermediates and packed parts only) gives the same
+ * result, each tile then splitting its factor rows itself. Errors: as kp_tucker, and
  * KP_ERR_ORDER for order < 2, KP_ERR_SHAPE if T's first mode is not 2 or the
  * parts of a factor differ in size, KP_ERR_NULL for Lim[k] without Lre[k]. */
 size_t kp_tucker_complex_workspace(const kp_tensor* T, const kp_matrix* const* Lre,

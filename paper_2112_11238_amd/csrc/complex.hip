@@ -103,6 +103,26 @@ int validate(const kp_tensor* T, const kp_matrix* const* Lre, const kp_matrix* c
   return KP_OK;
 }
 
+// Workspace of a validated call: `base` holds two ping-pong buffers for the
+// intermediates (only with two or more steps), then every factor part
+// packed k-contiguous; `planes` (BF16 split forms only) one set of
+// pre-split bf16 planes per factor part, placed after them.
+void complex_ws(const kp_tensor* T, const kp_matrix* const* Lre, const kp_matrix* const* Lim,
+                int conj, int prec, const ComplexPlan& p, size_t* base, size_t* planes) {
+  const size_t es = elem_size(T->dtype);
+  const int form = form_of(prec, T->dtype);
+  const bool split = form == FORM_BF16X3 || form == FORM_BF16X6;
+  *base = p.steps > 1 ? 2 * align_up(static_cast<size_t>(p.big) * es) : 0;
+  *planes = 0;
+  for (int k = 0; k < p.d; ++k) {
+    if (!Lre[k]) continue;
+    const kp_matrix a = applied(*Lre[k], conj);
+    const int parts = Lim[k] ? 2 : 1;
+    *base += parts * align_up(static_cast<size_t>(a.rows * a.cols) * es);
+    if (split) *planes += parts * align_up(split_planes_bytes(form, a.rows, a.cols));
+  }
+}
+
 }  // namespace
 }  // namespace kp
 
@@ -114,16 +134,9 @@ size_t kp_tucker_complex_workspace(const kp_tensor* T, const kp_matrix* const* L
                                    const kp_matrix* const* Lim, int conj, int prec) {
   ComplexPlan p;
   if (validate(T, Lre, Lim, conj, prec, &p)) return 0;
-  const size_t es = elem_size(T->dtype);
-  // two ping-pong buffers for the intermediates (only with two or more
-  // steps), then every factor part packed k-contiguous
-  size_t total = p.steps > 1 ? 2 * align_up(static_cast<size_t>(p.big) * es) : 0;
-  for (int k = 0; k < p.d; ++k) {
-    const int64_t nm = Lre[k] ? Lre[k]->rows * Lre[k]->cols : 0;
-    total += (Lre[k] ? 1 : 0) * align_up(static_cast<size_t>(nm) * es);
-    total += (Lim[k] ? 1 : 0) * align_up(static_cast<size_t>(nm) * es);
-  }
-  return total;
+  size_t base = 0, planes = 0;
+  complex_ws(T, Lre, Lim, conj, prec, p, &base, &planes);
+  return base + planes;
 }
 
 int kp_tucker_complex(const kp_tensor* T, const kp_matrix* const* Lre,
@@ -149,8 +162,16 @@ int kp_tucker_complex(const kp_tensor* T, const kp_matrix* const* Lre,
     if (Lim[k] && overlaps(S->data, sb, Lim[k]->data, matrix_span_bytes(*Lim[k])))
       return KP_ERR_ALIAS;
   }
-  const size_t need = kp_tucker_complex_workspace(T, Lre, Lim, conj, prec);
+  // the planes are used when the workspace has room for them (a workspace
+  // of `base` bytes runs the products with in-register splits)
+  size_t need = 0, planes_need = 0;
+  complex_ws(T, Lre, Lim, conj, prec, p, &need, &planes_need);
   if (need > 0 && (!ws || ws_bytes < need)) return KP_ERR_WORKSPACE;
+  const size_t planes_at = need;
+  if (planes_need > 0 && ws_bytes >= need + planes_need)
+    need += planes_need;
+  else
+    planes_need = 0;
   if (need > 0 && (overlaps(ws, need, S->data, sb) || overlaps(ws, need, T->data, tb)))
     return KP_ERR_ALIAS;
   for (int k = 0; k < p.d; ++k) {
@@ -203,6 +224,46 @@ int kp_tucker_complex(const kp_tensor* T, const kp_matrix* const* Lre,
       if (st) return st;
     }
   }
+  // products on wide tiles read their factor part's planes, split from the
+  // packed parts before the chain (KP_MAX_ORDER parts per launch)
+  const void* planes_re[KP_MAX_ORDER] = {};
+  const void* planes_im[KP_MAX_ORDER] = {};
+  if (planes_need > 0) {
+    char* at = w + planes_at;
+    SplitJobs jobs{};
+    auto add = [&](const kp_matrix& part, const void** slot) -> int {
+      SplitJob& J = jobs.job[jobs.count++];
+      J.L = part.data;
+      J.n = part.rows;
+      J.m = part.cols;
+      J.rs = part.rs;
+      J.cs = part.cs;
+      J.planes = at;
+      J.begin = jobs.total;
+      jobs.total += split_planes_tasks(J.n, J.m);
+      *slot = at;
+      at += align_up(split_planes_bytes(form, part.rows, part.cols));
+      if (jobs.count < KP_MAX_ORDER) return KP_OK;
+      const int r = hip_status(launch_split_planes(form, jobs, stream));
+      jobs = SplitJobs{};
+      return r;
+    };
+    for (int s = 0; s < p.steps; ++s) {
+      const int k = p.mode[s];
+      const ModeArgs a = mode_args(nullptr, nullptr, p.dims[s], T->d, k + 1, pre[k], kAccNone);
+      if (!mode_uses_wide(form, a, tile_override())) continue;
+      st = add(pre[k], &planes_re[k]);
+      if (st) return st;
+      if (Lim[k]) {
+        st = add(pim[k], &planes_im[k]);
+        if (st) return st;
+      }
+    }
+    if (jobs.count > 0) {
+      st = hip_status(launch_split_planes(form, jobs, stream));
+      if (st) return st;
+    }
+  }
   const void* src = T->data;
   int cur = -1;
   for (int s = 0; s < p.steps; ++s) {
@@ -215,13 +276,13 @@ int kp_tucker_complex(const kp_tensor* T, const kp_matrix* const* Lre,
       dst = pp[cur];
     }
     ModeArgs a = mode_args(src, dst, p.dims[s], T->d, k + 1, pre[k], kAccNone);
-    st = hip_status(launch_mode(form, a, tile_override(), stream));
+    st = hip_status(launch_mode_planes(form, a, tile_override(), planes_re[k], stream));
     if (st) return st;
     if (Lim[k]) {
       // dst += i s (src x Im(L)), combined in the product's epilogue
       ModeArgs b =
           mode_args(src, dst, p.dims[s], T->d, k + 1, pim[k], conj ? kAccSubI : kAccAddI);
-      st = hip_status(launch_mode(form, b, tile_override(), stream));
+      st = hip_status(launch_mode_planes(form, b, tile_override(), planes_im[k], stream));
       if (st) return st;
     }
     src = dst;

@@ -435,6 +435,26 @@ def test_workspace_counts_split_planes(lib, L):
     assert lib.kp_tucker_workspace(ctypes.byref(T1), arr1, 6) == 13 * 7 * 3 * 1024
 
 
+def test_complex_workspace_counts_split_planes(lib, L):
+    # BF16 split forms: after the intermediates and the packed factor parts,
+    # one plane set per factor part as applied (n x m, also for the conjugate
+    # transpose, whose factors are given m x n); FP32 native counts none
+    dims, rows = [2, 181, 200, 197], [204, 185, 200]
+    for conj in (0, 1):
+        shp = [(dims[k + 1], rows[k]) if conj else (rows[k], dims[k + 1]) for k in range(3)]
+        Re = mlist(L, [matrix(L, r, c, 1) for r, c in shp])
+        Im = mlist(L, [matrix(L, r, c, 1) for r, c in shp[:2]] + [None])
+        T = tensor(L, dims, dtype=1)
+        base = lib.kp_tucker_complex_workspace(ctypes.byref(T), Re, Im, conj, 0)
+        assert base > 0
+        for prec, planes in ((3, 2), (6, 3)):
+            want = sum(parts * ((((n + 15) // 16) * ((m + 31) // 32) * planes * 1024 + 255)
+                                // 256 * 256)
+                       for n, m, parts in zip(rows, dims[1:], (2, 2, 1)))
+            assert lib.kp_tucker_complex_workspace(ctypes.byref(T), Re, Im, conj, prec) == \
+                base + want
+
+
 @pytest.mark.parametrize("seed", range(8))
 def test_planned_order_minimises_flops(lib, L, seed):
     rng = np.random.default_rng(900 + seed)

@@ -66,6 +66,51 @@ def test_tucker_complex_matches_oracle(kp, form, prec, case, conj):
     assert np.all(np.abs(got.imag - ref.imag) <= b)
 
 
+@pytest.mark.parametrize("prec", ["bf16x3", "bf16x6"])
+@pytest.mark.parametrize("conj", [False, True])
+def test_complex_presplit_planes_bitwise(kp, prec, conj):
+    """Split-form products on wide tiles (n > 176) read bf16 planes of the
+    packed factor parts, split once per call. The same call with a
+    workspace that holds only the intermediates and the packed parts (each
+    tile then splits its rows itself) must agree with it bit for bit, and
+    both with the oracle within the form's bound. Ragged: rows past n in the
+    last tile, a k tail in the last step; the third mode runs on a k-loop
+    tile without planes."""
+    import ctypes
+    from paper_2112_11238_amd import ops
+    m, n = (181, 200, 64), (204, 185, 40)
+    T, Ls = kp_workloads.complex_problem(77, m, n, conj)
+    Td = dev(T, torch.complex64)
+    Ld = [dev(L, torch.complex64) for L in Ls]
+    say("complex presplit planes", prec, "conj" if conj else "")
+    S_full = kp.tucker_complex(Td, Ld, conj=conj, prec=prec)
+
+    lb = ops.lib()
+    td = ops._tdesc(torch.view_as_real(Td), True)
+    Lv = [torch.view_as_real(L) for L in Ld]
+    rarr = ops._mlist([ops._mdesc(v[..., 0]) for v in Lv][::-1])
+    iarr = ops._mlist([ops._mdesc(v[..., 1]) for v in Lv][::-1])
+    c = 1 if conj else 0
+    full = lb.kp_tucker_complex_workspace(ctypes.byref(td), rarr, iarr, c, ops._prec(prec))
+    base = lb.kp_tucker_complex_workspace(ctypes.byref(td), rarr, iarr, c, ops._prec("native"))
+    assert 0 < base < full                    # the planes take room of their own
+    S_inreg = torch.empty_like(S_full)
+    sd = ops._tdesc(torch.view_as_real(S_inreg), True)
+    ws = torch.empty(base, dtype=torch.uint8, device="cuda")
+    st = lb.kp_tucker_complex(ctypes.byref(td), rarr, iarr, ctypes.byref(sd), c, ops._prec(prec),
+                              ws.data_ptr(), base, ops._stream())
+    assert st == 0
+    torch.cuda.synchronize()
+    assert torch.equal(torch.view_as_real(S_full), torch.view_as_real(S_inreg))
+
+    T64, L64 = seen(T, torch.complex64), [seen(L, torch.complex64) for L in Ls]
+    ref = oracle.cttucker(T64, L64) if conj else oracle.ztucker(T64, L64)
+    got = S_full.to(torch.complex128).cpu().numpy()
+    b = bound(T64, L64, conj, prec, torch.float32)
+    assert np.all(np.abs(got.real - ref.real) <= b)
+    assert np.all(np.abs(got.imag - ref.imag) <= b)
+
+
 def test_fourier_transform_and_inverse(kp):
     shape = (64, 48, 30)
     rng = np.random.default_rng(9)
