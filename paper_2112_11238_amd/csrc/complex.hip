@@ -23,17 +23,33 @@ namespace {
 
 constexpr int kPT = 256;
 
-// dst[i * cols + j] = A(i, j) = src[i * rs + j * cs] for an rows x cols
-// matrix: the factor part as applied, packed k-contiguous.
+// One factor part to pack: dst[i * cols + j] = A(i, j) = src[i * rs + j * cs]
+// for an rows x cols matrix (the part as applied, packed k-contiguous);
+// begin: its first element in the launch's element range.
+struct PackJob {
+  const void* src;
+  int64_t rows, cols, rs, cs;
+  void* dst;
+  int64_t begin;
+};
+struct PackJobs {
+  PackJob job[2 * KP_MAX_ORDER];
+  int count;
+  int64_t total;
+};
+
+// Every part of a call in one launch: element e (grid-stride) belongs to
+// the job whose range holds it.
 template <typename E>
-__global__ __launch_bounds__(kPT) void pack_kernel(const E* __restrict__ src, int64_t rows,
-                                                   int64_t cols, int64_t rs, int64_t cs,
-                                                   E* __restrict__ dst) {
-  const int64_t total = rows * cols;
-  for (int64_t e = blockIdx.x * static_cast<int64_t>(kPT) + threadIdx.x; e < total;
+__global__ __launch_bounds__(kPT) void pack_kernel(PackJobs jobs) {
+  for (int64_t e = blockIdx.x * static_cast<int64_t>(kPT) + threadIdx.x; e < jobs.total;
        e += static_cast<int64_t>(gridDim.x) * kPT) {
-    const int64_t i = e / cols, j = e - (e / cols) * cols;
-    dst[e] = src[i * rs + j * cs];
+    int j = 0;
+    while (j + 1 < jobs.count && e >= jobs.job[j + 1].begin) ++j;
+    const PackJob& J = jobs.job[j];
+    const int64_t loc = e - J.begin;
+    const int64_t i = loc / J.cols, c = loc - i * J.cols;
+    static_cast<E*>(J.dst)[loc] = static_cast<const E*>(J.src)[i * J.rs + c * J.cs];
   }
 }
 
@@ -189,80 +205,85 @@ int kp_tucker_complex(const kp_tensor* T, const kp_matrix* const* Lre,
   char* w = static_cast<char*>(ws);
   const size_t buf = align_up(static_cast<size_t>(p.big) * es);
   char* pp[2] = {w, w + buf};
-  // factor parts as applied (transposed for the conjugate form), packed
-  // k-contiguous so the product kernels stage them with 16-byte loads
+  // Factor parts as applied (transposed for the conjugate form). A part
+  // whose product runs on a wide tile with the workspace's room for planes
+  // is split into bf16 planes straight from its strided view; every other
+  // part is packed k-contiguous into its workspace slot, so its product
+  // stages it with 16-byte loads. One launch packs all parts, one splits up
+  // to KP_MAX_ORDER.
   char* fw = w + (p.steps > 1 ? 2 * buf : 0);
+  char* at = w + planes_at;
   kp_matrix pre[KP_MAX_ORDER], pim[KP_MAX_ORDER];
-  auto pack = [&](const kp_matrix& L, kp_matrix* out) -> int {
+  const void* planes_re[KP_MAX_ORDER] = {};
+  const void* planes_im[KP_MAX_ORDER] = {};
+  PackJobs packs{};
+  SplitJobs splits{};
+  // the view the product of part L reads (*out) and, with planes, where
+  // they go (*slot); slots in the workspace's order (modes 1..d, real part
+  // first)
+  auto place = [&](const kp_matrix& L, bool planes, kp_matrix* out, const void** slot) -> int {
     const kp_matrix a = applied(L, conj);
     *out = a;
+    const int64_t total = a.rows * a.cols;
+    char* packed = fw;
+    fw += align_up(static_cast<size_t>(total) * es);
+    if (planes) {
+      SplitJob& J = splits.job[splits.count++];
+      J.L = a.data;
+      J.n = a.rows;
+      J.m = a.cols;
+      J.rs = a.rs;
+      J.cs = a.cs;
+      J.planes = at;
+      J.begin = splits.total;
+      splits.total += split_planes_tasks(J.n, J.m);
+      *slot = at;
+      at += align_up(split_planes_bytes(form, a.rows, a.cols));
+      if (splits.count < KP_MAX_ORDER) return KP_OK;
+      const int r = hip_status(launch_split_planes(form, splits, stream));
+      splits = SplitJobs{};
+      return r;
+    }
     out->rs = a.cols;
     out->cs = 1;
-    out->data = fw;
-    const int64_t total = a.rows * a.cols;
-    fw += align_up(static_cast<size_t>(total) * es);
+    out->data = packed;
     if (total == 0) return KP_OK;
-    const int64_t blocks = (total + kPT - 1) / kPT;
-    const unsigned grid = static_cast<unsigned>(blocks < 1024 ? blocks : 1024);
-    if (T->dtype == KP_F64)
-      hipLaunchKernelGGL(pack_kernel<double>, dim3(grid), dim3(kPT), 0, stream,
-                         static_cast<const double*>(a.data), a.rows, a.cols, a.rs, a.cs,
-                         static_cast<double*>(out->data));
-    else
-      hipLaunchKernelGGL(pack_kernel<float>, dim3(grid), dim3(kPT), 0, stream,
-                         static_cast<const float*>(a.data), a.rows, a.cols, a.rs, a.cs,
-                         static_cast<float*>(out->data));
-    return hip_status(hipGetLastError());
+    PackJob& J = packs.job[packs.count++];
+    J.src = a.data;
+    J.rows = a.rows;
+    J.cols = a.cols;
+    J.rs = a.rs;
+    J.cs = a.cs;
+    J.dst = packed;
+    J.begin = packs.total;
+    packs.total += total;
+    return KP_OK;
   };
-  for (int k = 0; k < p.d; ++k) {
-    if (Lre[k]) {
-      st = pack(*Lre[k], &pre[k]);
-      if (st) return st;
-    }
+  for (int s = 0; s < p.steps; ++s) {
+    const int k = p.mode[s];
+    const ModeArgs shape =
+        mode_args(nullptr, nullptr, p.dims[s], T->d, k + 1, applied(*Lre[k], conj), kAccNone);
+    const bool planes = planes_need > 0 && mode_uses_wide(form, shape, tile_override());
+    st = place(*Lre[k], planes, &pre[k], &planes_re[k]);
+    if (st) return st;
     if (Lim[k]) {
-      st = pack(*Lim[k], &pim[k]);
+      st = place(*Lim[k], planes, &pim[k], &planes_im[k]);
       if (st) return st;
     }
   }
-  // products on wide tiles read their factor part's planes, split from the
-  // packed parts before the chain (KP_MAX_ORDER parts per launch)
-  const void* planes_re[KP_MAX_ORDER] = {};
-  const void* planes_im[KP_MAX_ORDER] = {};
-  if (planes_need > 0) {
-    char* at = w + planes_at;
-    SplitJobs jobs{};
-    auto add = [&](const kp_matrix& part, const void** slot) -> int {
-      SplitJob& J = jobs.job[jobs.count++];
-      J.L = part.data;
-      J.n = part.rows;
-      J.m = part.cols;
-      J.rs = part.rs;
-      J.cs = part.cs;
-      J.planes = at;
-      J.begin = jobs.total;
-      jobs.total += split_planes_tasks(J.n, J.m);
-      *slot = at;
-      at += align_up(split_planes_bytes(form, part.rows, part.cols));
-      if (jobs.count < KP_MAX_ORDER) return KP_OK;
-      const int r = hip_status(launch_split_planes(form, jobs, stream));
-      jobs = SplitJobs{};
-      return r;
-    };
-    for (int s = 0; s < p.steps; ++s) {
-      const int k = p.mode[s];
-      const ModeArgs a = mode_args(nullptr, nullptr, p.dims[s], T->d, k + 1, pre[k], kAccNone);
-      if (!mode_uses_wide(form, a, tile_override())) continue;
-      st = add(pre[k], &planes_re[k]);
-      if (st) return st;
-      if (Lim[k]) {
-        st = add(pim[k], &planes_im[k]);
-        if (st) return st;
-      }
-    }
-    if (jobs.count > 0) {
-      st = hip_status(launch_split_planes(form, jobs, stream));
-      if (st) return st;
-    }
+  if (packs.count > 0) {
+    const int64_t blocks = (packs.total + kPT - 1) / kPT;
+    const unsigned grid = static_cast<unsigned>(blocks < 1024 ? blocks : 1024);
+    if (T->dtype == KP_F64)
+      hipLaunchKernelGGL(pack_kernel<double>, dim3(grid), dim3(kPT), 0, stream, packs);
+    else
+      hipLaunchKernelGGL(pack_kernel<float>, dim3(grid), dim3(kPT), 0, stream, packs);
+    st = hip_status(hipGetLastError());
+    if (st) return st;
+  }
+  if (splits.count > 0) {
+    st = hip_status(launch_split_planes(form, splits, stream));
+    if (st) return st;
   }
   const void* src = T->data;
   int cur = -1;
