@@ -111,6 +111,51 @@ def test_complex_presplit_planes_bitwise(kp, prec, conj):
     assert np.all(np.abs(got.imag - ref.imag) <= b)
 
 
+def test_complex_planes_split_in_two_launches(kp):
+    """Wide tiles forced on every mode of an order-5 complex problem: ten
+    factor parts read as planes, more than one split launch holds (eight),
+    so they are split in two launches. Bit for bit against the same call
+    with a workspace without room for planes, and within the bound of the
+    oracle. Tiny ragged sizes: every tile is mostly rows past n and k past m."""
+    import ctypes
+    from paper_2112_11238_amd import ops
+    m, n = (5, 7, 6, 4, 9), (6, 5, 8, 3, 7)
+    T, Ls = kp_workloads.complex_problem(78, m, n)
+    Td = dev(T, torch.complex64)
+    Ld = [dev(L, torch.complex64) for L in Ls]
+    say("complex planes, two split launches")
+    lb = ops.lib()
+    td = ops._tdesc(torch.view_as_real(Td), True)
+    Lv = [torch.view_as_real(L) for L in Ld]
+    rarr = ops._mlist([ops._mdesc(v[..., 0]) for v in Lv][::-1])
+    iarr = ops._mlist([ops._mdesc(v[..., 1]) for v in Lv][::-1])
+    p = ops._prec("bf16x3")
+    full = lb.kp_tucker_complex_workspace(ctypes.byref(td), rarr, iarr, 0, p)
+    base = lb.kp_tucker_complex_workspace(ctypes.byref(td), rarr, iarr, 0, ops._prec("native"))
+    assert 0 < base < full
+    out = []
+    kp.force_tile(2, 4, 32, 2, 2, 3)
+    try:
+        for nbytes in (full, base):
+            S = torch.empty(n, dtype=torch.complex64, device="cuda")
+            sd = ops._tdesc(torch.view_as_real(S), True)
+            ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+            st = lb.kp_tucker_complex(ctypes.byref(td), rarr, iarr, ctypes.byref(sd), 0, p,
+                                      ws.data_ptr(), nbytes, ops._stream())
+            assert st == 0
+            torch.cuda.synchronize()
+            out.append(S)
+    finally:
+        kp.force_tile(0)
+    assert torch.equal(torch.view_as_real(out[0]), torch.view_as_real(out[1]))
+    T64, L64 = seen(T, torch.complex64), [seen(L, torch.complex64) for L in Ls]
+    ref = oracle.ztucker(T64, L64)
+    got = out[0].to(torch.complex128).cpu().numpy()
+    b = bound(T64, L64, False, "bf16x3", torch.float32)
+    assert np.all(np.abs(got.real - ref.real) <= b)
+    assert np.all(np.abs(got.imag - ref.imag) <= b)
+
+
 def test_fourier_transform_and_inverse(kp):
     shape = (64, 48, 30)
     rng = np.random.default_rng(9)
