@@ -581,7 +581,6 @@ int kp_tucker(const kp_tensor* T, const kp_matrix* const* L, kp_tensor* S, int p
     if (fused[s] && fuse_step(p, s, T->d, L, form, &pa)) {
       pa.X = src;
       pa.Y = dst_of(s + 1);
-      pa.stream_out = s + 1 == p.count - 1;
       st = hip_status(launch_pair(form, pa, stream));
       if (st) return st;
       src = pa.Y;

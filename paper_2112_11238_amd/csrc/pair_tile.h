@@ -50,9 +50,6 @@ struct PairArgs {
   const void* L2;  // n2 x m2
   int64_t Il, m1, m2, n1, n2, Ir;
   int64_t rs1, cs1, rs2, cs2;
-  // the pass writes the call's result, read by nothing after it in the call:
-  // the lead-layout pass then stores with the non-temporal hint
-  int stream_out = 0;
 };
 
 // NB1*16 >= n1, NB2*16 >= n2. Workgroup tiles tile0, tile0 + tstep, ... <
@@ -445,14 +442,7 @@ __device__ __forceinline__ void lead_pair_run(const PairArgs& a, int64_t wave0, 
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     const uint32_t ybase = static_cast<uint32_t>(r) * nn * 4u;
-    if (vstore && a.stream_out) {
-      // non-temporal (cache policy 2): the result streams past the caches
-      for (uint32_t e = lane; e < nn / 4; e += 64) {
-        const f4v_t v = *reinterpret_cast<const f4v_t*>(yw + 4 * e);
-        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), yrs,
-                                               static_cast<int>(ybase + 16 * e), 0, 2);
-      }
-    } else if (vstore) {
+    if (vstore) {
       for (uint32_t e = lane; e < nn / 4; e += 64) {
         const f4v_t v = *reinterpret_cast<const f4v_t*>(yw + 4 * e);
         __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), yrs,
