@@ -22,6 +22,8 @@ CASES = [
     ("f64", "native", ((200, 200, 200), (200, 200, 200)), ((37, 50, 23), (41, 17, 29))),
     ("f32", "bf16x6", ((64, 48, 80, 40), (72, 56, 40, 64)), ((9, 30, 17, 5), (12, 19, 33, 7))),
     ("f32", "native", ((16,) * 5, (24,) * 5), ((5, 7, 6), (8, 3, 9))),
+    # wide tiles (n > 176) reading factor planes split into the scratch
+    ("f32", "bf16x3", ((181, 200, 40), (204, 185, 30)), ((9, 30, 17), (12, 19, 33))),
 ]
 
 
